@@ -1,0 +1,185 @@
+"""ctypes front end of the CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline import this package; the library's product path never does. The
+oracle shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OK, E_INVALID, E_CONFLICT, E_CAPACITY, E_NOMEM, E_RANGE = 0, -1, -2, -3, -4, -6
+
+_lib = None
+
+_i64p = C.POINTER(C.c_int64)
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+_u64p = C.POINTER(C.c_uint64)
+_u32p = C.POINTER(C.c_uint32)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.orc_load.argtypes = [C.c_int64, C.c_int64, _i64p, _i64p, _f64p, C.POINTER(vp)]
+    lib.orc_free.argtypes = [vp]
+    lib.orc_info.argtypes = [vp, _i64p, _i64p, _i64p, _i64p, _i64p]
+    lib.orc_edges.argtypes = [vp, _i32p, _i32p, _f64p]
+    lib.orc_count.argtypes = [vp, C.c_double, _i64p]
+    lib.orc_count_multi.argtypes = [vp, _f64p, C.c_int, _i64p]
+    lib.orc_enumerate.argtypes = [vp, C.c_double, _i32p, C.c_int64, _i32p, C.c_int64, _i64p]
+    lib.orc_expected.argtypes = [vp, _f64p, _i64p, _u64p, _i64p]
+    lib.orc_grad.argtypes = [vp, _i64p, C.c_int64, _f64p]
+    lib.orc_edge_local.argtypes = [vp, _f64p, C.c_int, _i64p, C.c_int64, _i64p]
+    lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.orc_sample_edge.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64]
+    lib.orc_sample_edge.restype = C.c_int64
+    lib.orc_sample.argtypes = [vp, _f64p, C.c_int, C.c_int64, C.c_int32, C.c_uint64, _f64p, _i64p]
+    lib.orc_num_threads.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"oracle {what} failed with code {code}")
+        self.code = code
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+class OracleGraph:
+    """Canonical uncertain signed graph held by the oracle."""
+
+    def __init__(self, n, src, dst, p):
+        lib = _load()
+        src = np.ascontiguousarray(src, dtype=np.int64)
+        dst = np.ascontiguousarray(dst, dtype=np.int64)
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        h = C.c_void_p()
+        rc = lib.orc_load(int(n), int(src.shape[0]), _p(src, _i64p), _p(dst, _i64p),
+                          _p(p, _f64p), C.byref(h))
+        if rc != OK:
+            raise OracleError(rc, "load")
+        self._h = h
+        self._lib = lib
+        vals = [C.c_int64() for _ in range(5)]
+        lib.orc_info(h, *[C.byref(v) for v in vals])
+        self.n, self.m, self.self_loops, self.dups, self.max_deg = [v.value for v in vals]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.orc_free(h)
+            self._h = None
+
+    def edges(self):
+        lo = np.empty(self.m, np.int32)
+        hi = np.empty(self.m, np.int32)
+        p = np.empty(self.m, np.float64)
+        self._lib.orc_edges(self._h, _p(lo, _i32p), _p(hi, _i32p), _p(p, _f64p))
+        return lo, hi, p
+
+    def count(self, t):
+        out = np.zeros(2, np.int64)
+        rc = self._lib.orc_count(self._h, float(t), _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "count")
+        return int(out[0]), int(out[1])
+
+    def count_multi(self, ts):
+        ts = np.ascontiguousarray(ts, dtype=np.float64)
+        out = np.zeros((ts.shape[0], 2), np.int64)
+        rc = self._lib.orc_count_multi(self._h, _p(ts, _f64p), int(ts.shape[0]), _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "count_multi")
+        return out
+
+    def enumerate(self, t, cap=None):
+        """(balanced, unbalanced) as int32 [k,3] arrays, rows sorted within and across."""
+        counts = np.zeros(2, np.int64)
+        if cap is None:
+            nb, nu = self.count(t)
+            cap = (nb, nu)
+        bal = np.empty((max(cap[0], 1), 3), np.int32)
+        unb = np.empty((max(cap[1], 1), 3), np.int32)
+        rc = self._lib.orc_enumerate(self._h, float(t), _p(bal, _i32p), int(cap[0]),
+                                     _p(unb, _i32p), int(cap[1]), _p(counts, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "enumerate")
+        return bal[:counts[0]].copy(), unb[:counts[1]].copy()
+
+    def expected(self):
+        """(E, T, S) with S the exact fixed-point sum of s as a Python int."""
+        E = C.c_double()
+        T = C.c_int64()
+        lo = C.c_uint64()
+        hi = C.c_int64()
+        rc = self._lib.orc_expected(self._h, C.byref(E), C.byref(T), C.byref(lo), C.byref(hi))
+        if rc != OK:
+            raise OracleError(rc, "expected")
+        return E.value, T.value, (hi.value << 64) + lo.value
+
+    def grad(self, eids=None):
+        eids = np.arange(self.m, dtype=np.int64) if eids is None else np.ascontiguousarray(eids, np.int64)
+        out = np.empty(eids.shape[0], np.float64)
+        rc = self._lib.orc_grad(self._h, _p(eids, _i64p), int(eids.shape[0]), _p(out, _f64p))
+        if rc != OK:
+            raise OracleError(rc, "grad")
+        return out
+
+    def edge_local(self, ts, eids=None):
+        ts = np.atleast_1d(np.ascontiguousarray(ts, dtype=np.float64))
+        eids = np.arange(self.m, dtype=np.int64) if eids is None else np.ascontiguousarray(eids, np.int64)
+        out = np.zeros((eids.shape[0], ts.shape[0], 2), np.int64)
+        rc = self._lib.orc_edge_local(self._h, _p(ts, _f64p), int(ts.shape[0]), _p(eids, _i64p),
+                                      int(eids.shape[0]), _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "edge_local")
+        return out
+
+    def sample(self, ts, k, worlds, seed):
+        ts = np.atleast_1d(np.ascontiguousarray(ts, dtype=np.float64))
+        est = np.zeros((worlds, ts.shape[0], 2), np.float64)
+        sums = np.zeros((worlds, ts.shape[0], 2), np.int64)
+        rc = self._lib.orc_sample(self._h, _p(ts, _f64p), int(ts.shape[0]), int(k), int(worlds),
+                                  C.c_uint64(seed), _p(est, _f64p), _p(sums, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "sample")
+        return est, sums
+
+
+def load(n, src, dst, p) -> OracleGraph:
+    return OracleGraph(n, src, dst, p)
+
+
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib.orc_philox4x32_10(_p(c, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def sample_edge(seed, world, i, m) -> int:
+    return int(_load().orc_sample_edge(C.c_uint64(seed), C.c_uint32(world), C.c_uint64(i), int(m)))

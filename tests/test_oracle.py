@@ -1,0 +1,403 @@
+"""Pins for the CPU oracle: each check ties it to something other than itself.
+
+* exact rational brute force over all vertex triples (the paper's four-term P_bal,
+  Section 3, and its two definitions taken literally);
+* closed forms: triangle count trace(A^3)/6, signed triangle parity trace(S^3)/6,
+  E = T/2 when every P+ is 0.5;
+* invariants: Lemma 1 (reversal), Lemma 2 (probability range), Lemma 3 (cut-off),
+  relabelling invariance, the edge-sampling identity sum_e local(e) = 3 |B|
+  (proof of the edge-sampling unbiasedness theorem, Section 6.2);
+* hand-derived single-triangle cases in tests/golden/triangle_cases.txt;
+* Philox4x32-10 against rocRAND's engine compiled for the host.
+"""
+import os
+import shutil
+import subprocess
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_14084_amd import inputs
+from tests import bruteforce as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "triangle_cases.txt")
+TS = [0.5, 0.5625, 0.6, 0.75, 0.8, 0.9375, 1.0]
+
+
+def tiny_graphs():
+    """(n, lo, hi) tiny graphs for brute force: dense and sparse."""
+    out = []
+    for seed, (n, dens) in enumerate([(8, 0.9), (10, 0.6), (12, 0.5), (13, 0.35), (14, 0.7), (9, 1.0)]):
+        out.append(inputs.random_graph(n, dens, 100 + seed))
+    return out
+
+
+def load(n, lo, hi, p):
+    return oracle.load(n, lo, hi, p)
+
+
+# ---------------------------------------------------------------- golden cases
+
+def golden_cases():
+    rows = []
+    for line in open(GOLDEN):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        name, a, b, c, t, cls = line.split()
+        rows.append((name, float(a), float(b), float(c), float(t), cls))
+    return rows
+
+
+@pytest.mark.parametrize("case", golden_cases(), ids=lambda r: r[0])
+def test_golden_single_triangle(case):
+    name, a, b, c, t, cls = case
+    # the fixture itself agrees with the exact four-term sum
+    pb = bf.p_bal(F(a), F(b), F(c))
+    exact = "B" if pb >= F(t) else ("U" if 1 - pb > F(t) else "N")
+    assert exact == cls, (name, pb)
+    # and the oracle reaches it on a 3-vertex graph, for every labelling of the edges
+    for perm in [(0, 1, 2), (2, 0, 1), (1, 2, 0)]:
+        ps = [a, b, c]
+        g = load(3, [0, 0, 1], [1, 2, 2], [ps[perm[0]], ps[perm[1]], ps[perm[2]]])
+        nb, nu = g.count(t)
+        got = "B" if nb else ("U" if nu else "N")
+        assert (nb, nu) in [(1, 0), (0, 1), (0, 0)]
+        assert got == cls, (name, perm, nb, nu)
+
+
+def test_lemma3_cutoff_formula():
+    """Lemma 3's final cut-off x = (2p^2 - 2p + t)/(4p^2 - 4p + 1): the triangle (p, p, x)
+    has P_bal exactly t, and in d units |1 - 2x| = (2t - 1)/(1 - 2p)^2."""
+    for p in [F(7, 8), F(15, 16), F(1), F(3, 4)]:
+        for t in [F(3, 4), F(9, 16), F(5, 8)]:
+            x = (2 * p * p - 2 * p + t) / (4 * p * p - 4 * p + 1)
+            assert bf.p_bal(p, p, x) == t
+            assert abs(1 - 2 * x) == (2 * t - 1) / (1 - 2 * p) ** 2
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("dist", ["dyadic16", "tri", "uniform", "beta0505", "certain"])
+def test_counts_and_lists_match_bruteforce(dist):
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()):
+        p = inputs.draw_p(lo.shape[0], dist, 7 + gi)
+        g = load(n, lo, hi, p)
+        for t in TS:
+            bal, unb = bf.classify_all(n, lo, hi, p, t)
+            assert g.count(t) == (len(bal), len(unb)), (dist, gi, t)
+            ob, ou = g.enumerate(t)
+            assert [tuple(r) for r in ob] == sorted(bal)
+            assert [tuple(r) for r in ou] == sorted(unb)
+
+
+@pytest.mark.parametrize("dist", ["dyadic16", "uniform", "tri"])
+def test_expected_matches_exact_rational(dist):
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()):
+        p = inputs.draw_p(lo.shape[0], dist, 11 + gi)
+        g = load(n, lo, hi, p)
+        E, T, _ = g.expected()
+        exact = bf.expected(n, lo, hi, p)
+        if dist in ("dyadic16", "tri"):
+            assert F(E) == exact  # every step is exact on dyadic inputs
+        else:
+            # per triangle: |s| <= 1 carries the roundings of three d values and two
+            # products (< 2^-50 relative) and the 2^-63 fixed-point rounding; E is
+            # rounded once at the end
+            assert abs(F(E) - exact) <= F(T, 2 ** 62) + F(T, 2 ** 51) + abs(exact) * F(1, 2 ** 52)
+
+
+@pytest.mark.parametrize("dist", ["dyadic16", "uniform"])
+def test_grad_two_point_identity(dist):
+    """E is affine in each P+(e), so dE/dp_e = E(p_e=1) - E(p_e=0) exactly."""
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()[:4]):
+        p = inputs.draw_p(lo.shape[0], dist, 21 + gi)
+        g = load(n, lo, hi, p)
+        gr = g.grad()
+        for e in range(lo.shape[0]):
+            exact = bf.grad_two_point(n, lo, hi, p, e)
+            if dist == "dyadic16":
+                assert F(gr[e]) == exact
+            else:
+                # at most n - 2 terms, each |d d'| <= 1 with two rounded d values and a
+                # rounded product (< 2^-51 relative) plus the 2^-63 fixed-point step
+                assert abs(F(gr[e]) - exact) <= F(n, 2 ** 62) + F(n, 2 ** 50) + abs(exact) * F(1, 2 ** 52)
+
+
+def test_grad_central_difference():
+    n, lo, hi = inputs.chung_lu_graph(300, 2.5, 2500.0, 5)
+    p = inputs.draw_p(lo.shape[0], "uniform_05_95", 3)
+    g = load(n, lo, hi, p)
+    gr = g.grad()
+    E0, _, _ = g.expected()
+    rng = np.random.default_rng(0)
+    h = 1e-3
+    for e in rng.integers(0, lo.shape[0], 25):
+        pp = p.copy(); pp[e] = p[e] + h
+        pm = p.copy(); pm[e] = p[e] - h
+        Ep = load(n, lo, hi, pp).expected()[0]
+        Em = load(n, lo, hi, pm).expected()[0]
+        fd = (Ep - Em) / (pp[e] - pm[e])
+        # E is affine in p_e: only the rounding of E enters, ~ulp(E)/h
+        assert abs(fd - gr[e]) <= 1e-8 * max(1.0, abs(E0)), (e, fd, gr[e])
+
+
+# ---------------------------------------------------------------- closed forms
+
+def dense_adj(n, lo, hi, vals=None):
+    A = np.zeros((n, n))
+    v = np.ones(lo.shape[0]) if vals is None else vals
+    A[lo, hi] = v
+    A[hi, lo] = v
+    return A
+
+
+def test_triangle_total_trace_formula():
+    n, lo, hi = inputs.chung_lu_graph()
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = load(n, lo, hi, p)
+    A = dense_adj(n, lo, hi)
+    T = int(round(np.trace(A @ A @ A) / 6))
+    _, T2, _ = g.expected()
+    assert T2 == T
+    nb, nu = g.count(0.5)  # c = 0 splits every triangle into exactly one class
+    assert nb + nu == T
+
+
+def test_certain_signs_reduce_to_signed_counting():
+    """P+ in {0,1}: a triangle is balanced iff it has an odd number of '+' edges, i.e.
+    iff the product of its +-1 signs is +1; sum over triangles = trace(S^3)/6."""
+    n, lo, hi = inputs.chung_lu_graph(600, 2.5, 6000.0, 9)
+    p = inputs.draw_p(lo.shape[0], "certain", 4)
+    g = load(n, lo, hi, p)
+    A = dense_adj(n, lo, hi)
+    S = dense_adj(n, lo, hi, np.where(p > 0.5, 1.0, -1.0))
+    T = int(round(np.trace(A @ A @ A) / 6))
+    signed = int(round(np.trace(S @ S @ S) / 6))
+    n_bal = (T + signed) // 2
+    for t in [0.5, 0.6, 0.8, 0.99]:
+        assert g.count(t) == (n_bal, T - n_bal)
+    assert g.count(1.0) == (n_bal, 0)
+
+
+def test_all_half_special_case():
+    n, lo, hi = inputs.chung_lu_graph(500, 2.5, 5000.0, 2)
+    p = np.full(lo.shape[0], 0.5)
+    g = load(n, lo, hi, p)
+    E, T, _ = g.expected()
+    assert E == T / 2
+    assert g.count(0.5) == (T, 0)
+    assert g.count(0.5000001) == (0, 0)
+    assert np.all(g.grad() == 0.0)
+
+
+def test_single_coin_flip_edge_unclassifies():
+    """Every triangle through a P+ = 0.5 edge has P_bal = 0.5 exactly: balanced at
+    t = 0.5, unclassified above (Section 3 remark on unclassified triangles)."""
+    n, lo, hi = inputs.random_graph(12, 0.8, 3)
+    p = inputs.draw_p(lo.shape[0], "certain", 5)
+    p[0] = 0.5
+    g = load(n, lo, hi, p)
+    loc = g.edge_local([0.5, 0.51], [0])[0]
+    A = dense_adj(n, lo, hi)
+    through = int((A[lo[0]] * A[hi[0]]).sum())
+    assert through > 0
+    assert loc[0].tolist() == [through, 0]
+    assert loc[1].tolist() == [0, 0]
+
+
+# ---------------------------------------------------------------- lemmas
+
+def test_lemma1_reversal_counts():
+    """Lemma 1: flipping every P+ to 1-P+ swaps balanced and unbalanced. With the >= / >
+    asymmetry of the two definitions, on the dyadic grid (s is a multiple of 2^-9):
+      |B^t(G')| = |U^(t - 2^-11)(G)|   and   |U^t(G')| = |B^(t + 2^-11)(G)|."""
+    for gi in range(3):
+        n, lo, hi = inputs.chung_lu_graph(400, 2.5, 4000.0, 30 + gi)
+        p = inputs.draw_p(lo.shape[0], "dyadic16", 40 + gi)
+        g = load(n, lo, hi, p)
+        gr = load(n, lo, hi, 1.0 - p)
+        for t in [0.5625, 0.75, 0.875, 0.9375]:
+            b2, u2 = gr.count(t)
+            assert b2 == g.count(t - 2.0 ** -11)[1]
+            assert u2 == g.count(t + 2.0 ** -11)[0]
+
+
+def test_lemma2_and_lemma3_hold_on_classified():
+    """Every classified triangle has min |d| >= c (Lemma 2) and, with D its largest |d|,
+    min |d| >= c / D^2 (Lemma 3 in d units). Checked in exact rationals."""
+    n, lo, hi = inputs.chung_lu_graph(500, 2.5, 6000.0, 12)
+    p = inputs.draw_p(lo.shape[0], "dyadic16", 13)
+    g = load(n, lo, hi, p)
+    E = {(int(a), int(b)): F(float(x)) for a, b, x in zip(lo, hi, p)}
+    for t in [0.5625, 0.75, 0.9375]:
+        c = 2 * F(t) - 1
+        bal, unb = g.enumerate(t)
+        for tri in list(bal) + list(unb):
+            i, j, k = map(int, tri)
+            ds = [abs(1 - 2 * E[(i, j)]), abs(1 - 2 * E[(i, k)]), abs(1 - 2 * E[(j, k)])]
+            assert min(ds) >= c
+            D = max(ds)
+            assert min(ds) * D * D >= c
+
+
+def test_relabelling_invariance():
+    n, lo, hi = inputs.chung_lu_graph(700, 2.5, 7000.0, 21)
+    p = inputs.draw_p(lo.shape[0], "uniform", 22)
+    g = load(n, lo, hi, p)
+    perm = np.random.default_rng(5).permutation(n)
+    s2, d2 = perm[lo], perm[hi]
+    g2 = load(n, s2, d2, p)
+    for t in [0.5, 0.6, 0.8]:
+        assert g.count(t) == g2.count(t)
+    E1, T1, S1 = g.expected()
+    E2, T2, S2 = g2.expected()
+    assert (E1, T1, S1) == (E2, T2, S2)
+    # gradients agree edge by edge once edge ids are mapped through the relabelling
+    lo2, hi2, _ = g2.edges()
+    key2 = {(int(a), int(b)): e for e, (a, b) in enumerate(zip(lo2, hi2))}
+    gr1, gr2 = g.grad(), g2.grad()
+    for e in range(0, lo.shape[0], 7):
+        a, b = int(perm[lo[e]]), int(perm[hi[e]])
+        assert gr1[e] == gr2[key2[(min(a, b), max(a, b))]]
+    inv = np.argsort(perm)
+    b1, _ = g.enumerate(0.6)
+    b2, _ = g2.enumerate(0.6)
+    back = np.sort(inv[b2], axis=1)
+    assert sorted(map(tuple, back)) == [tuple(r) for r in b1]
+
+
+# ---------------------------------------------------------------- sampling
+
+def test_edge_local_sums_to_three_times_count():
+    n, lo, hi = inputs.chung_lu_graph()
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = load(n, lo, hi, p)
+    ts = [0.5, 0.6, 0.75, 0.9]
+    loc = g.edge_local(ts)
+    tot = loc.sum(axis=0)
+    for j, t in enumerate(ts):
+        nb, nu = g.count(t)
+        assert tot[j, 0] == 3 * nb and tot[j, 1] == 3 * nu
+
+
+def test_sampler_replay_and_unbiased():
+    n, lo, hi = inputs.chung_lu_graph()
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = load(n, lo, hi, p)
+    ts = [0.6, 0.8]
+    k, W, seed = 200, 256, 0xC0FFEE1234
+    est, sums = g.sample(ts, k, W, seed)
+    # replay two worlds by hand from the same Philox draws
+    for w in (0, 77):
+        eids = np.array([oracle.sample_edge(seed, w, i, g.m) for i in range(k)], np.int64)
+        loc = g.edge_local(ts, eids)
+        assert np.array_equal(loc.sum(axis=0), sums[w])
+        for j in range(len(ts)):
+            for q in range(2):
+                assert est[w, j, q] == (float(sums[w, j, q]) * float(g.m)) / (3.0 * float(k))
+    # mean over worlds is unbiased: within 4 standard errors of the exact count
+    exact = np.array([g.count(t) for t in ts], dtype=np.float64)
+    mean = est.mean(axis=0)
+    se = est.std(axis=0, ddof=1) / np.sqrt(W)
+    assert np.all(np.abs(mean - exact) <= 4 * se + 1e-9), (mean, exact, se)
+
+
+def test_sample_edge_convention():
+    """Draw i of world w: key (seed_lo ^ w, seed_hi), counter (i_lo, i_hi, 0, 0); the edge
+    is the high word of the 128-bit product (x1:x0) * m (the Philox block itself is
+    pinned to rocRAND below)."""
+    for seed, w, i, m in [(0x0123456789ABCDEF, 0, 0, 1000), (5, 1023, 2 ** 33 + 7, 15701420),
+                          (2 ** 64 - 1, 77, 999, 3)]:
+        x = oracle.philox4x32_10([i & 0xFFFFFFFF, i >> 32, 0, 0],
+                                 [(seed & 0xFFFFFFFF) ^ w, seed >> 32])
+        x64 = (int(x[1]) << 32) | int(x[0])
+        assert oracle.sample_edge(seed, w, i, m) == (x64 * m) >> 64
+
+
+def test_sample_edge_is_uniform():
+    m = 97
+    draws = np.array([oracle.sample_edge(7, 3, i, m) for i in range(20000)])
+    assert draws.min() >= 0 and draws.max() < m
+    cnt = np.bincount(draws, minlength=m)
+    chi2 = ((cnt - 20000 / m) ** 2 / (20000 / m)).sum()
+    assert chi2 < 200  # 96 degrees of freedom; p ~ 1e-8 beyond this
+
+
+ROCRAND_SRC = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char** argv) {
+  unsigned long long seed = strtoull(argv[1], 0, 0), idx = strtoull(argv[2], 0, 0);
+  rocrand_device::philox4x32_10_engine e(seed, 0, 4ull * idx);
+  unsigned a = e(), b = e(), c = e(), d = e();
+  printf("%u %u %u %u\n", a, b, c, d);
+  return 0;
+}
+"""
+
+
+def test_philox_matches_rocrand_host_engine(tmp_path):
+    """rocRAND's engine(seed, 0, 4i) starts at counter (i_lo, i_hi, 0, 0) with key
+    (seed_lo, seed_hi); its first four outputs are one Philox4x32-10 block."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    src = tmp_path / "rr.cpp"
+    src.write_text(ROCRAND_SRC)
+    exe = tmp_path / "rr"
+    subprocess.run([hipcc, "-x", "c++", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", "-O1",
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    for seed, idx in [(0, 0), (1, 0), (0x0123456789ABCDEF, 5), (0xFFFFFFFFFFFFFFFF, 2 ** 32 + 3),
+                      (42, 123456789)]:
+        out = subprocess.run([str(exe), str(seed), str(idx)], check=True, capture_output=True,
+                             text=True).stdout.split()
+        ref = [int(x) for x in out]
+        got = oracle.philox4x32_10([idx & 0xFFFFFFFF, idx >> 32, 0, 0],
+                                   [seed & 0xFFFFFFFF, seed >> 32])
+        assert list(map(int, got)) == ref, (seed, idx)
+
+
+# ---------------------------------------------------------------- loading and errors
+
+def test_load_canonicalises_dirty_input():
+    n, lo, hi = inputs.chung_lu_graph(300, 2.5, 2000.0, 3)
+    p = inputs.draw_p(lo.shape[0], "uniform", 4)
+    s, d, pp = inputs.dirty_edges(lo, hi, p, seed=5, n=n)
+    g = load(n, s, d, pp)
+    lo2, hi2, p2 = g.edges()
+    assert np.array_equal(lo2, lo) and np.array_equal(hi2, hi) and np.array_equal(p2, p)
+    assert g.self_loops == 5 and g.dups == int(lo.shape[0] * 0.1)
+
+
+@pytest.mark.parametrize("bad", ["nan", "neg", "big", "conflict", "id"])
+def test_load_errors(bad):
+    src = np.array([0, 1, 2], np.int64)
+    dst = np.array([1, 2, 0], np.int64)
+    p = np.array([0.1, 0.2, 0.3])
+    n = 3
+    want = oracle.E_INVALID
+    if bad == "nan":
+        p[1] = np.nan
+    elif bad == "neg":
+        p[1] = -1e-300
+    elif bad == "big":
+        p[1] = np.nextafter(1.0, 2.0)
+    elif bad == "conflict":
+        src = np.append(src, 1); dst = np.append(dst, 0); p = np.append(p, 0.5)
+        want = oracle.E_CONFLICT
+    elif bad == "id":
+        dst[0] = 3
+    with pytest.raises(oracle.OracleError) as ei:
+        load(n, src, dst, p)
+    assert ei.value.code == want
+
+
+def test_threshold_range():
+    g = load(3, [0, 0, 1], [1, 2, 2], [0.1, 0.2, 0.3])
+    for t in [0.49999, 1.0000001, float("nan")]:
+        with pytest.raises(oracle.OracleError):
+            g.count(t)
