@@ -1,0 +1,193 @@
+/*
+ * utri.h -- C ABI of libutri: exact counting and enumeration of uncertain balanced
+ * and unbalanced triangles, the expected balanced count and its per-edge gradient,
+ * and the edge-sampling estimator, on MI355X (gfx950).
+ *
+ * Model (arXiv 2602.14084, Section 3): an undirected graph whose edges all exist,
+ * each with a probability P+(e) in [0,1] that its sign is positive, signs
+ * independent. A triangle is balanced when it has an odd number of '+' edges; its
+ * probability of being balanced is the four-term sum of Section 3, equal to
+ * P_bal = (1 - s)/2 with s = d1*d2*d3 and d = 1 - 2*P+. At a threshold t in [0.5, 1]
+ * (the paper assumes t >= 0.5) a triangle is
+ *   uncertain balanced   iff P_bal   >= t   (Definition "Uncertain Balanced Triangle")
+ *   uncertain unbalanced iff P_unbal >  t   (Definition "Uncertain Unbalanced Triangle").
+ * Decisions are taken in FP64 as: d = 1.0 - 2.0*p; c = 2.0*t - 1.0; the three d of a
+ * triangle sorted ascending by value; s = (x*y)*z, each product rounded (no fused
+ * multiply-add); balanced iff s <= -c, unbalanced iff s > c. Counts are exact
+ * integers; a result depends on the graph and t only, never on thread scheduling.
+ *
+ * Conventions shared by every call:
+ *  - Return value: UTRI_OK (0) or a negative utri_status. No call aborts or exits.
+ *  - Vertex ids are 0..n-1 with n < 2^31; the canonical graph has m < 2^31 edges.
+ *    Canonical edge e is (lo[e], hi[e]) with lo < hi; edge ids are ranks in
+ *    ascending (lo, hi) order. Self-loops are dropped and counted; an exact
+ *    duplicate (either orientation, same P+) is merged and counted; a duplicate
+ *    with a different P+ is UTRI_E_CONFLICT (an edge has one P+, Section 3).
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream). Every kernel
+ *    of a call is enqueued on it. Calls that return scalars through host pointers
+ *    (counts, E, sizes) wait for that stream before returning; calls whose outputs
+ *    are device arrays return as soon as the work is enqueued.
+ *  - Buffers passed in are owned by the caller and are not retained after the call
+ *    returns. The handle owns every device copy it makes. A handle must not be used
+ *    from two host threads or two streams at the same time.
+ *  - Device pointers must be device memory of the current HIP device.
+ */
+#ifndef UTRI_H
+#define UTRI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct utri_graph utri_graph;
+
+typedef enum {
+    UTRI_OK = 0,
+    UTRI_E_INVALID = -1,   /* bad argument: NULL pointer, id out of range, P+ NaN or outside [0,1], t outside [0.5,1] */
+    UTRI_E_CONFLICT = -2,  /* the same undirected edge given twice with different P+ */
+    UTRI_E_CAPACITY = -3,  /* an enumeration output buffer is too small; sizes are still reported */
+    UTRI_E_NOMEM = -4,     /* device or host allocation failed */
+    UTRI_E_HIP = -5,       /* a HIP runtime call failed */
+    UTRI_E_RANGE = -6      /* n or m does not fit the int32 ids of the library */
+} utri_status;
+
+/* Search methods (both give identical results). */
+enum {
+    UTRI_PLAIN = 0,      /* forward edge iteration over every triangle (Algorithm "Baseline UBTE/UBTC", Section 4) */
+    UTRI_PRUNED = 1,     /* rows cut to |d| >= c before the walk (Lemma 2, Section 5) */
+    UTRI_PRUNED_L3 = 2   /* PRUNED plus a per-edge cut |d_vw| * |d_uv| * max|d_u.| >= c (Lemma 3, Section 5) */
+};
+
+/* Which classes to count or list (Section 3: "balanced and/or unbalanced"). */
+enum { UTRI_BAL = 1, UTRI_UNBAL = 2, UTRI_BOTH = 3 };
+
+/* Pointer kinds for inputs / outputs that may live on either side. */
+enum { UTRI_HOST_PTR = 0, UTRI_DEVICE_PTR = 1 };
+
+/* Sampling schemes. */
+enum { UTRI_SAMPLE_EDGE = 0 };
+
+/*
+ * Build a graph handle (Definition "Uncertain Signed Graph", Section 3).
+ * src, dst: int64 [m_in] endpoint ids in [0, n); p: FP64 [m_in] P+ of each input edge.
+ * ptr_kind says whether the three arrays are host or device memory.
+ * Preprocessing (kept for every later query, as the paper pre-sorts its data,
+ * Section 7): canonical sorted edge list, symmetric adjacency with rows in
+ * Absolute Edge Order (|d| descending, then neighbour id; Definitions "Absolute Edge
+ * Value" / "Absolute Edge Order", Section 5), per-row hash tables, and the degree
+ * orientation of Definition "Node Order" (Section 4) with vertices relabelled by it.
+ * Errors: UTRI_E_INVALID (NULL with m_in > 0, id out of range, bad P+),
+ * UTRI_E_CONFLICT, UTRI_E_RANGE (n >= 2^31 or m >= 2^31), UTRI_E_NOMEM, UTRI_E_HIP.
+ * On error *out is NULL.
+ */
+int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int64_t m_in,
+                    int64_t n, int ptr_kind, void* hip_stream, utri_graph** out);
+
+/* Release a handle and all its device memory. NULL is accepted. */
+int utri_graph_free(utri_graph* g);
+
+/* Sizes of the canonical graph. Any output pointer may be NULL. */
+int utri_graph_info(const utri_graph* g, int64_t* n, int64_t* m, int64_t* self_loops_dropped,
+                    int64_t* dups_merged, int64_t* max_deg);
+
+/* Canonical edges in edge-id order: lo, hi int32 [m], p FP64 [m] (host or device per
+ * ptr_kind; any may be NULL). These ids index the gradient and the sampler. */
+int utri_graph_edges(const utri_graph* g, int32_t* lo, int32_t* hi, double* p, int ptr_kind,
+                     void* hip_stream);
+
+/* Replace every P+ (FP64 [m] in edge-id order, host or device). The topology is kept;
+ * rows are re-sorted into Absolute Edge Order for the new values.
+ * Errors: UTRI_E_INVALID for NaN or values outside [0,1] (the handle keeps its old P+). */
+int utri_graph_set_p(utri_graph* g, const double* p, int ptr_kind, void* hip_stream);
+
+/*
+ * Counting problem (Definition "The Uncertain Balanced/Unbalanced Triangle Counting
+ * Problem", Section 3) at threshold t in [0.5, 1].
+ * out[0] = number of uncertain balanced triangles, out[1] = unbalanced (host int64 [2]);
+ * a class not selected by `which` is reported as 0. method: UTRI_PLAIN / UTRI_PRUNED /
+ * UTRI_PRUNED_L3. Waits for the stream.
+ */
+int utri_count(utri_graph* g, double t, int method, int which, int64_t out[2], void* hip_stream);
+
+/* Counts at nt thresholds (any order, 1 <= nt <= 64) from one walk at the smallest
+ * one: out host int64 [nt][2]. Waits for the stream. */
+int utri_count_batch(utri_graph* g, const double* t, int nt, int method, int64_t* out,
+                     void* hip_stream);
+
+/*
+ * Enumeration problem (Section 3) at t. bal / unbal: device int32 [cap][3] triples of
+ * original vertex ids, each triple sorted ascending. out_counts (host int64 [2]) gets
+ * the full list sizes. sorted = 1 sorts each list lexicographically; sorted = 0 leaves
+ * it in a deterministic walk order. A class not selected by `which` is neither
+ * written nor counted. If a list exceeds its capacity nothing is written for it and
+ * UTRI_E_CAPACITY is returned with the sizes filled in, so the caller can retry.
+ * Waits for the stream.
+ */
+int utri_enumerate(utri_graph* g, double t, int method, int which, int32_t* bal, int64_t cap_b,
+                   int32_t* unbal, int64_t cap_u, int64_t out_counts[2], int sorted,
+                   void* hip_stream);
+
+/*
+ * Expected number of balanced triangles E = sum over all triangles of P_bal (Section 3
+ * four-term sum) = (T - sum s)/2. The sum of s is exact in 128-bit fixed point (each s
+ * rounded to a multiple of 2^-62, ties to even) and E = (T*2^62 - S) * 2^-63 is
+ * rounded once, so E does not depend on summation order. E: host double. Waits.
+ */
+int utri_expected(utri_graph* g, double* E, void* hip_stream);
+
+/*
+ * Gradient dE/dP+(e) for every edge: the sum over triangles (e, f, g) of d_f * d_g
+ * (derivative of (1 - d_e d_f d_g)/2 with dd/dp = -2), each product rounded to FP64,
+ * summed in the same fixed point and rounded once. grad: device FP64 [m] in edge-id
+ * order. Each edge's sum is produced by one owner; no global atomics.
+ */
+int utri_expected_grad(utri_graph* g, double* grad, void* hip_stream);
+
+/*
+ * Local counts of Algorithm "Improved Edge Local Search" (Section 6.2): for each listed
+ * edge id, the uncertain balanced / unbalanced triangles through it at each threshold.
+ * eids: device int64 [k]; out: device int64 [k][nt][2]; 1 <= nt <= 64, t any order.
+ */
+int utri_edge_local(utri_graph* g, const double* t, int nt, const int64_t* eids, int64_t k,
+                    int64_t* out, void* hip_stream);
+
+/*
+ * Edge-sampling estimator (Algorithm "Baseline Edge Sampling" with the improved local
+ * search, Section 6.2), `worlds` independent replicates of k draws each. Draw i of
+ * replicate w is Philox4x32-10 (Salmon et al., SC'11) with key (seed_lo ^ w, seed_hi)
+ * and counter (i_lo, i_hi, 0, 0); the edge is the high 64 bits of (x1:x0) * m.
+ * est: device FP64 [worlds][nt][2] = m * (sum of local counts) / (3k), computed as
+ * ((double)sum * (double)m) / (3.0 * (double)k). scheme must be UTRI_SAMPLE_EDGE.
+ */
+int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
+                int scheme, double* est, void* hip_stream);
+
+/*
+ * Batched queries in one persistent launch: exact counts at nt thresholds (one walk at
+ * the smallest, binned by s) together with `worlds` replicates of the edge-sampling
+ * estimator at the same thresholds. exact: device int64 [nt][2]; est: device FP64
+ * [worlds][nt][2] (either may be NULL to skip that part). use_graph = 1 captures the
+ * launch sequence into a hipGraph on the first call with a given shape and replays it
+ * afterwards (t and seed are re-read from device buffers on every replay).
+ */
+int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
+               int64_t* exact, double* est, int use_graph, void* hip_stream);
+
+/*
+ * Launch-shape autotuner: times the walk and sampler kernels on this graph over a small
+ * grid of work-group counts and sample-chunk sizes and keeps the fastest for later
+ * calls. If cache_path is not NULL the choice is stored there as one JSON line keyed by
+ * (n, m, max degree) and reused by later handles of the same shape.
+ */
+int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream);
+
+/* Human-readable text for a status code. */
+const char* utri_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UTRI_H */

@@ -1,0 +1,632 @@
+// api.hip -- the extern "C" entry points declared in include/utri.h: argument checks,
+// threshold ordering, scratch plumbing, stream handling and result read-back. All
+// arithmetic of a query runs in the kernels of walk.hip, sample.hip and backward.hip.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "utri_internal.h"
+
+namespace {
+
+inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+inline bool t_ok(double t) { return t >= 0.5 && t <= 1.0; }  // false for NaN
+
+// Sort thresholds ascending; order[j] = original index of the j-th smallest.
+int sort_thresholds(const double* t, int nt, std::vector<double>& cvals,
+                    std::vector<int32_t>& order) {
+    if (!t || nt < 1 || nt > 64) return UTRI_E_INVALID;
+    for (int j = 0; j < nt; j++)
+        if (!t_ok(t[j])) return UTRI_E_INVALID;
+    order.resize(nt);
+    for (int j = 0; j < nt; j++) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t[a] < t[b]; });
+    cvals.resize(nt);
+    for (int j = 0; j < nt; j++) cvals[j] = utri_c_of_t(t[order[j]]);
+    return UTRI_OK;
+}
+
+// Upload the sorted thresholds and their order into scratch device buffers.
+int upload_thresholds(utri_graph* g, const std::vector<double>& cvals,
+                      const std::vector<int32_t>& order, hipStream_t s, double** dc,
+                      int32_t** dord) {
+    void *pc, *po;
+    UTRI_TRY(utri_scratch(g, SCR_CVALS, sizeof(double) * 64, &pc));
+    UTRI_TRY(utri_scratch(g, SCR_ORDER, sizeof(int32_t) * 64, &po));
+    UTRI_HIP_TRY(hipMemcpyAsync(pc, cvals.data(), sizeof(double) * cvals.size(),
+                                hipMemcpyHostToDevice, s));
+    UTRI_HIP_TRY(hipMemcpyAsync(po, order.data(), sizeof(int32_t) * order.size(),
+                                hipMemcpyHostToDevice, s));
+    *dc = (double*)pc;
+    *dord = (int32_t*)po;
+    return UTRI_OK;
+}
+
+int check_graph(const utri_graph* g) { return g ? UTRI_OK : UTRI_E_INVALID; }
+
+// ------------------------------------------------------------------ enumeration sort
+
+__global__ void k_tri_keys(const int32_t* __restrict__ tri, int64_t cnt, unsigned nb,
+                           uint64_t* __restrict__ k_lo, uint32_t* __restrict__ k_hi,
+                           uint32_t* __restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    k_lo[i] = ((uint64_t)(uint32_t)tri[3 * i + 1] << nb) | (uint64_t)(uint32_t)tri[3 * i + 2];
+    k_hi[i] = (uint32_t)tri[3 * i];
+    idx[i] = (uint32_t)i;
+}
+
+__global__ void k_tri_key_first(const int32_t* __restrict__ tri, const uint32_t* __restrict__ idx,
+                                int64_t cnt, uint32_t* __restrict__ k) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) k[i] = (uint32_t)tri[3 * (int64_t)idx[i]];
+}
+
+__global__ void k_tri_gather(const int32_t* __restrict__ tri, const uint32_t* __restrict__ idx,
+                             int64_t cnt, int32_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t j = idx[i];
+    out[3 * i] = tri[3 * j];
+    out[3 * i + 1] = tri[3 * j + 1];
+    out[3 * i + 2] = tri[3 * j + 2];
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+inline int nblk(int64_t n) { return (int)((n + 255) / 256); }
+
+__global__ void k_check_eids(const int64_t* __restrict__ eids, int64_t k, int64_t m,
+                             uint32_t* __restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k && (eids[i] < 0 || eids[i] >= m)) atomicOr(flag, 1u);
+}
+
+template <class K, class V>
+int radix_pairs(utri_graph* g, const K* kin, K* kout, const V* vin, V* vout, int64_t cnt,
+                unsigned bits, hipStream_t s) {
+    size_t bytes = 0;
+    UTRI_HIP_TRY(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)cnt, 0,
+                                           bits, s));
+    void* tmp;
+    UTRI_TRY(utri_scratch(g, SCR_TEMP, bytes, &tmp));
+    UTRI_HIP_TRY(rocprim::radix_sort_pairs(tmp, bytes, kin, kout, vin, vout, (size_t)cnt, 0,
+                                           bits, s));
+    return UTRI_OK;
+}
+
+// Lexicographic sort of cnt int32 triples in place (two stable LSD radix passes).
+int sort_triples(utri_graph* g, int32_t* tri, int64_t cnt, hipStream_t s) {
+    if (cnt <= 1) return UTRI_OK;
+    unsigned nb = 1;
+    while (((int64_t)1 << nb) < g->n) nb++;
+    void *pa, *pb, *pc, *pd;
+    UTRI_TRY(utri_scratch(g, SCR_SORT_A, sizeof(uint64_t) * cnt * 2, &pa));
+    UTRI_TRY(utri_scratch(g, SCR_SORT_B, sizeof(uint32_t) * cnt * 2, &pb));
+    UTRI_TRY(utri_scratch(g, SCR_SORT_C, sizeof(uint32_t) * cnt * 2, &pc));
+    UTRI_TRY(utri_scratch(g, SCR_SORT_D, sizeof(int32_t) * cnt * 3, &pd));
+    uint64_t* k64 = (uint64_t*)pa;
+    uint32_t* k32 = (uint32_t*)pb;
+    uint32_t* idx = (uint32_t*)pc;
+    hipLaunchKernelGGL(k_tri_keys, dim3(nblk(cnt)), dim3(256), 0, s, tri, cnt, nb, k64, k32, idx);
+    UTRI_HIP_TRY(hipGetLastError());
+    UTRI_TRY(radix_pairs(g, k64, k64 + cnt, idx, idx + cnt, cnt, 2 * nb, s));
+    hipLaunchKernelGGL(k_tri_key_first, dim3(nblk(cnt)), dim3(256), 0, s, tri, idx + cnt, cnt, k32);
+    UTRI_HIP_TRY(hipGetLastError());
+    UTRI_TRY(radix_pairs(g, k32, k32 + cnt, idx + cnt, idx, cnt, nb, s));
+    int32_t* tmp = (int32_t*)pd;
+    hipLaunchKernelGGL(k_tri_gather, dim3(nblk(cnt)), dim3(256), 0, s, tri, idx, cnt, tmp);
+    hipLaunchKernelGGL(k_copy_i32, dim3(nblk(3 * cnt)), dim3(256), 0, s, tmp, 3 * cnt, tri);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+// ------------------------------------------------------------------ shared query pieces
+
+int walk_prepare_for(utri_graph* g, int method, double c, hipStream_t s, int64_t** items,
+                     int64_t** nitems, int32_t** len) {
+    const double c_rows = (method == UTRI_PLAIN) ? 0.0 : c;
+    return utri_walk_prepare(g, c_rows, 0, s, items, nitems, len);
+}
+
+WalkParams base_params(int method, double c) {
+    WalkParams wp;
+    wp.c = c;
+    wp.lemma3 = (method == UTRI_PRUNED_L3) ? 1 : 0;
+    wp.c_l3 = c * (1.0 - 0x1p-50);
+    return wp;
+}
+
+int count_impl(utri_graph* g, double t, int method, int64_t out[2], hipStream_t s) {
+    const double c = utri_c_of_t(t);
+    int64_t *items, *nitems;
+    int32_t* len;
+    UTRI_TRY(walk_prepare_for(g, method, c, s, &items, &nitems, &len));
+    void* acc;
+    UTRI_TRY(utri_scratch(g, SCR_ACC, sizeof(uint64_t) * 4, &acc));
+    UTRI_TRY(utri_fill_u64(acc, 0, 2, s));
+    WalkParams wp = base_params(method, c);
+    wp.acc = (unsigned long long*)acc;
+    UTRI_TRY(utri_walk_launch(g, WALK_COUNT, wp, items, nitems, len, 0, s));
+    uint64_t h[2] = {0, 0};
+    UTRI_HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    out[0] = (int64_t)h[0];
+    out[1] = (int64_t)h[1];
+    return UTRI_OK;
+}
+
+// Launch sequence of the batch path (also what gets captured into a hipGraph).
+int batch_sequence(utri_graph* g, const double* dc, const int32_t* dord, int nt, double cmin,
+                   int64_t k, int32_t worlds, const uint64_t* seed_dev, int64_t* exact,
+                   double* est, hipStream_t s) {
+    int64_t *items = nullptr, *nitems = nullptr;
+    int32_t* len = nullptr;
+    int32_t* slen = nullptr;
+    void *hw = nullptr, *hs = nullptr;
+    WalkParams wp = base_params(UTRI_PRUNED, cmin);
+    if (exact) {
+        UTRI_TRY(utri_walk_prepare(g, cmin, 0, s, &items, &nitems, &len));
+        UTRI_TRY(utri_scratch(g, SCR_HIST2, sizeof(uint64_t) * 2 * (nt + 1), &hw));
+        UTRI_TRY(utri_fill_u64(hw, 0, 2 * (nt + 1), s));
+        wp.acc = (unsigned long long*)hw;
+        wp.cvals = dc;
+        wp.nt = nt;
+    }
+    SampleParams sp;
+    if (est && k > 0 && worlds > 0) {
+        UTRI_TRY(utri_sym_prepare(g, cmin, s, &slen));
+        const size_t nh = (size_t)worlds * 2 * (nt + 1);
+        UTRI_TRY(utri_scratch(g, SCR_HIST, sizeof(uint64_t) * nh, &hs));
+        UTRI_TRY(utri_fill_u64(hs, 0, (int64_t)nh, s));
+        sp.cvals = dc;
+        sp.nt = nt;
+        sp.cmin = cmin;
+        sp.seed_dev = seed_dev;
+        sp.k = k;
+        sp.worlds = worlds;
+        sp.chunk = g->sample_chunk;
+        sp.hist = (unsigned long long*)hs;
+    }
+    if (!items) {
+        // no walk part: the kernel still needs a valid (zero) item count
+        void* pn;
+        UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 4, &pn));
+        nitems = (int64_t*)pn;
+    }
+    UTRI_TRY(utri_batch_launch(g, wp, items, nitems, len, 0, sp, slen, s));
+    if (exact) UTRI_TRY(utri_finalize_launch((const unsigned long long*)hw, 1, nt, dord, g->m, 1, exact, nullptr, s));
+    if (sp.hist) UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k, nullptr, est, s));
+    return UTRI_OK;
+}
+
+// ------------------------------------------------------------------ autotune cache
+
+std::string cache_key(const utri_graph* g) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "\"n\": %lld, \"m\": %lld, \"max_deg\": %lld", (long long)g->n,
+             (long long)g->m, (long long)g->max_deg);
+    return buf;
+}
+
+void apply_cache(utri_graph* g, const char* path) {
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    const std::string key = cache_key(g);
+    while (fgets(line, sizeof(line), f)) {
+        if (!strstr(line, key.c_str())) continue;
+        const char* a = strstr(line, "\"walk_blocks_per_cu\": ");
+        const char* b = strstr(line, "\"sample_chunk\": ");
+        if (a) g->walk_blocks_per_cu = std::max(1, atoi(a + 22));
+        if (b) g->sample_chunk = std::max(64, atoi(b + 16) / 64 * 64);
+    }
+    fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* utri_strerror(int code) {
+    switch (code) {
+        case UTRI_OK: return "ok";
+        case UTRI_E_INVALID: return "invalid argument";
+        case UTRI_E_CONFLICT: return "an edge was given twice with different P+";
+        case UTRI_E_CAPACITY: return "output capacity too small";
+        case UTRI_E_NOMEM: return "out of memory";
+        case UTRI_E_HIP: return "HIP runtime error";
+        case UTRI_E_RANGE: return "graph too large for 32-bit ids";
+        default: return "unknown status";
+    }
+}
+
+int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int64_t m_in,
+                    int64_t n, int ptr_kind, void* hip_stream, utri_graph** out) {
+    if (!out) return UTRI_E_INVALID;
+    *out = nullptr;
+    if (n < 0 || m_in < 0) return UTRI_E_INVALID;
+    if (ptr_kind != UTRI_HOST_PTR && ptr_kind != UTRI_DEVICE_PTR) return UTRI_E_INVALID;
+    if (m_in > 0 && (!src || !dst || !p)) return UTRI_E_INVALID;
+    if (n >= ((int64_t)1 << 31)) return UTRI_E_RANGE;
+    utri_graph* g = nullptr;
+    int rc = utri_load_internal(src, dst, p, m_in, n, ptr_kind, as_stream(hip_stream), &g);
+    if (rc != UTRI_OK) return rc;
+    apply_cache(g, getenv("UTRI_TUNE_CACHE"));
+    *out = g;
+    return UTRI_OK;
+}
+
+int utri_graph_free(utri_graph* g) {
+    if (!g) return UTRI_OK;
+    (void)hipDeviceSynchronize();
+    utri_free_graph_internal(g);
+    return UTRI_OK;
+}
+
+int utri_graph_info(const utri_graph* g, int64_t* n, int64_t* m, int64_t* self_loops_dropped,
+                    int64_t* dups_merged, int64_t* max_deg) {
+    UTRI_TRY(check_graph(g));
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (self_loops_dropped) *self_loops_dropped = g->self_loops;
+    if (dups_merged) *dups_merged = g->dups;
+    if (max_deg) *max_deg = g->max_deg;
+    return UTRI_OK;
+}
+
+int utri_graph_edges(const utri_graph* g, int32_t* lo, int32_t* hi, double* p, int ptr_kind,
+                     void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (ptr_kind != UTRI_HOST_PTR && ptr_kind != UTRI_DEVICE_PTR) return UTRI_E_INVALID;
+    hipStream_t s = as_stream(hip_stream);
+    const hipMemcpyKind kind = ptr_kind == UTRI_HOST_PTR ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (g->m > 0) {
+        if (lo) UTRI_HIP_TRY(hipMemcpyAsync(lo, g->e_lo, sizeof(int32_t) * g->m, kind, s));
+        if (hi) UTRI_HIP_TRY(hipMemcpyAsync(hi, g->e_hi, sizeof(int32_t) * g->m, kind, s));
+        if (p) UTRI_HIP_TRY(hipMemcpyAsync(p, g->e_p, sizeof(double) * g->m, kind, s));
+    }
+    if (ptr_kind == UTRI_HOST_PTR) UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_graph_set_p(utri_graph* g, const double* p, int ptr_kind, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (ptr_kind != UTRI_HOST_PTR && ptr_kind != UTRI_DEVICE_PTR) return UTRI_E_INVALID;
+    if (g->m > 0 && !p) return UTRI_E_INVALID;
+    return utri_set_p_internal(g, p, ptr_kind, as_stream(hip_stream));
+}
+
+int utri_count(utri_graph* g, double t, int method, int which, int64_t out[2], void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!out || !t_ok(t)) return UTRI_E_INVALID;
+    if (method < UTRI_PLAIN || method > UTRI_PRUNED_L3) return UTRI_E_INVALID;
+    if (which < UTRI_BAL || which > UTRI_BOTH) return UTRI_E_INVALID;
+    int64_t r[2] = {0, 0};
+    UTRI_TRY(count_impl(g, t, method, r, as_stream(hip_stream)));
+    out[0] = (which & UTRI_BAL) ? r[0] : 0;
+    out[1] = (which & UTRI_UNBAL) ? r[1] : 0;
+    return UTRI_OK;
+}
+
+int utri_count_batch(utri_graph* g, const double* t, int nt, int method, int64_t* out,
+                     void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!out) return UTRI_E_INVALID;
+    if (method < UTRI_PLAIN || method > UTRI_PRUNED_L3) return UTRI_E_INVALID;
+    std::vector<double> cv;
+    std::vector<int32_t> order;
+    UTRI_TRY(sort_thresholds(t, nt, cv, order));
+    hipStream_t s = as_stream(hip_stream);
+    double* dc;
+    int32_t* dord;
+    UTRI_TRY(upload_thresholds(g, cv, order, s, &dc, &dord));
+    const double cmin = cv[0];
+    int64_t *items, *nitems;
+    int32_t* len;
+    UTRI_TRY(walk_prepare_for(g, method, cmin, s, &items, &nitems, &len));
+    void *acc, *dout;
+    UTRI_TRY(utri_scratch(g, SCR_ACC, sizeof(uint64_t) * 2 * (nt + 1), &acc));
+    UTRI_TRY(utri_scratch(g, SCR_OUT, sizeof(int64_t) * 2 * nt, &dout));
+    UTRI_TRY(utri_fill_u64(acc, 0, 2 * (nt + 1), s));
+    WalkParams wp = base_params(method, cmin);
+    wp.acc = (unsigned long long*)acc;
+    wp.cvals = dc;
+    wp.nt = nt;
+    UTRI_TRY(utri_walk_launch(g, WALK_HIST, wp, items, nitems, len, 0, s));
+    UTRI_TRY(utri_finalize_launch((const unsigned long long*)acc, 1, nt, dord, g->m, 1,
+                                  (int64_t*)dout, nullptr, s));
+    UTRI_HIP_TRY(hipMemcpyAsync(out, dout, sizeof(int64_t) * 2 * nt, hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_enumerate(utri_graph* g, double t, int method, int which, int32_t* bal, int64_t cap_b,
+                   int32_t* unbal, int64_t cap_u, int64_t out_counts[2], int sorted,
+                   void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!out_counts || !t_ok(t) || cap_b < 0 || cap_u < 0) return UTRI_E_INVALID;
+    if (method < UTRI_PLAIN || method > UTRI_PRUNED_L3) return UTRI_E_INVALID;
+    if (which < UTRI_BAL || which > UTRI_BOTH) return UTRI_E_INVALID;
+    hipStream_t s = as_stream(hip_stream);
+    const double c = utri_c_of_t(t);
+    int64_t *items, *nitems;
+    int32_t* len;
+    UTRI_TRY(walk_prepare_for(g, method, c, s, &items, &nitems, &len));
+    const int64_t bound = (int64_t)utri_walk_items_bound(g) + 1;
+    void *pc, *po, *ptot;
+    UTRI_TRY(utri_scratch(g, SCR_ICNT2, sizeof(int64_t) * 2 * bound, &pc));
+    UTRI_TRY(utri_scratch(g, SCR_IOFF2, sizeof(int64_t) * 2 * bound, &po));
+    UTRI_TRY(utri_scratch(g, SCR_OUT, sizeof(int64_t) * 4, &ptot));
+    int64_t* cnt_b = (int64_t*)pc;
+    int64_t* cnt_u = cnt_b + bound;
+    int64_t* off_b = (int64_t*)po;
+    int64_t* off_u = off_b + bound;
+    int64_t* tot = (int64_t*)ptot;
+    UTRI_TRY(utri_fill_u64(pc, 0, 2 * bound, s));
+    UTRI_TRY(utri_fill_u64(ptot, 0, 4, s));
+    WalkParams wp = base_params(method, c);
+    wp.cnt_b = cnt_b;
+    wp.cnt_u = cnt_u;
+    wp.which = which;
+    UTRI_TRY(utri_walk_launch(g, WALK_ENUM_COUNT, wp, items, nitems, len, 0, s));
+    UTRI_TRY(utri_scan_i64(g, cnt_b, off_b, bound, tot, s));
+    UTRI_TRY(utri_scan_i64(g, cnt_u, off_u, bound, tot + 1, s));
+    int64_t h[2] = {0, 0};
+    UTRI_HIP_TRY(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t nb = (which & UTRI_BAL) ? h[0] : 0;
+    const int64_t nu = (which & UTRI_UNBAL) ? h[1] : 0;
+    out_counts[0] = nb;
+    out_counts[1] = nu;
+    if (nb > cap_b || nu > cap_u) return UTRI_E_CAPACITY;
+    if ((nb > 0 && !bal) || (nu > 0 && !unbal)) return UTRI_E_INVALID;
+    if (nb == 0 && nu == 0) return UTRI_OK;
+    WalkParams wf = base_params(method, c);
+    wf.off_b = off_b;
+    wf.off_u = off_u;
+    wf.out_bal = bal;
+    wf.out_unbal = unbal;
+    wf.which = which;
+    UTRI_TRY(utri_walk_launch(g, WALK_ENUM_FILL, wf, items, nitems, len, 0, s));
+    if (sorted) {
+        if (nb > 1) UTRI_TRY(sort_triples(g, bal, nb, s));
+        if (nu > 1) UTRI_TRY(sort_triples(g, unbal, nu, s));
+    }
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_expected(utri_graph* g, double* E, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!E) return UTRI_E_INVALID;
+    hipStream_t s = as_stream(hip_stream);
+    int64_t *items, *nitems;
+    int32_t* len;
+    UTRI_TRY(utri_walk_prepare(g, 0.0, 0, s, &items, &nitems, &len));
+    void* acc;
+    UTRI_TRY(utri_scratch(g, SCR_ACC, sizeof(uint64_t) * 4, &acc));
+    UTRI_TRY(utri_fill_u64(acc, 0, 3, s));
+    WalkParams wp;
+    wp.acc = (unsigned long long*)acc;
+    UTRI_TRY(utri_walk_launch(g, WALK_EXPECTED, wp, items, nitems, len, 0, s));
+    uint64_t h[3] = {0, 0, 0};
+    UTRI_HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    // N = T * 2^62 - S, exact in 128 bits; E = N * 2^-63 rounded once
+    const unsigned __int128 T = (unsigned __int128)h[0];
+    const unsigned __int128 S = ((unsigned __int128)h[2] << 64) | (unsigned __int128)h[1];
+    const unsigned __int128 N = (T << 62) - S;
+    *E = utri_i128_to_double((int64_t)(uint64_t)(N >> 64), (uint64_t)N) * 0x1p-63;
+    return UTRI_OK;
+}
+
+int utri_expected_grad(utri_graph* g, double* grad, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (g->m > 0 && !grad) return UTRI_E_INVALID;
+    return utri_grad_launch(g, grad, as_stream(hip_stream));
+}
+
+int utri_edge_local(utri_graph* g, const double* t, int nt, const int64_t* eids, int64_t k,
+                    int64_t* out, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (k < 0 || (k > 0 && (!eids || !out))) return UTRI_E_INVALID;
+    std::vector<double> cv;
+    std::vector<int32_t> order;
+    UTRI_TRY(sort_thresholds(t, nt, cv, order));
+    if (k == 0) return UTRI_OK;
+    hipStream_t s = as_stream(hip_stream);
+    // edge ids come from the caller: check the range before any kernel indexes with them
+    UTRI_HIP_TRY(hipMemsetAsync(g->d_flags, 0, sizeof(uint32_t), s));
+    hipLaunchKernelGGL(k_check_eids, dim3(nblk(k)), dim3(256), 0, s, eids, k, g->m, g->d_flags);
+    UTRI_HIP_TRY(hipGetLastError());
+    uint32_t bad = 0;
+    UTRI_HIP_TRY(hipMemcpyAsync(&bad, g->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return UTRI_E_INVALID;
+    double* dc;
+    int32_t* dord;
+    UTRI_TRY(upload_thresholds(g, cv, order, s, &dc, &dord));
+    UTRI_TRY(utri_edge_local_launch(g, dc, dord, nt, eids, k, out, s));
+    // the threshold buffers are host vectors: wait before they go out of scope
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
+                int scheme, double* est, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (scheme != UTRI_SAMPLE_EDGE || k <= 0 || worlds <= 0 || !est) return UTRI_E_INVALID;
+    if (g->m == 0) return UTRI_E_INVALID;
+    std::vector<double> cv;
+    std::vector<int32_t> order;
+    UTRI_TRY(sort_thresholds(t, nt, cv, order));
+    hipStream_t s = as_stream(hip_stream);
+    double* dc;
+    int32_t* dord;
+    UTRI_TRY(upload_thresholds(g, cv, order, s, &dc, &dord));
+    int32_t* slen;
+    UTRI_TRY(utri_sym_prepare(g, cv[0], s, &slen));
+    const size_t nh = (size_t)worlds * 2 * (nt + 1);
+    void* hs;
+    UTRI_TRY(utri_scratch(g, SCR_HIST, sizeof(uint64_t) * nh, &hs));
+    UTRI_TRY(utri_fill_u64(hs, 0, (int64_t)nh, s));
+    SampleParams sp;
+    sp.cvals = dc;
+    sp.nt = nt;
+    sp.cmin = cv[0];
+    sp.seed = seed;
+    sp.k = k;
+    sp.worlds = worlds;
+    sp.chunk = g->sample_chunk;
+    sp.hist = (unsigned long long*)hs;
+    UTRI_TRY(utri_sample_launch(g, sp, slen, s));
+    UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k,
+                                  nullptr, est, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
+               int64_t* exact, double* est, int use_graph, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (est && (k <= 0 || worlds <= 0)) return UTRI_E_INVALID;
+    if (g->m == 0 && est) return UTRI_E_INVALID;
+    std::vector<double> cv;
+    std::vector<int32_t> order;
+    UTRI_TRY(sort_thresholds(t, nt, cv, order));
+    hipStream_t s = as_stream(hip_stream);
+    double* dc;
+    int32_t* dord;
+    UTRI_TRY(upload_thresholds(g, cv, order, s, &dc, &dord));
+    void* pseed;
+    UTRI_TRY(utri_scratch(g, SCR_SEED, sizeof(uint64_t), &pseed));
+    UTRI_HIP_TRY(hipMemcpyAsync(pseed, &seed, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    const uint64_t* sd = (const uint64_t*)pseed;
+    UtriBatchGraph& B = g->batch;
+    if (!use_graph) {
+        UTRI_TRY(batch_sequence(g, dc, dord, nt, cv[0], k, worlds, sd, exact, est, s));
+        UTRI_HIP_TRY(hipStreamSynchronize(s));
+        return UTRI_OK;
+    }
+    // Graphs are captured and replayed on a stream owned by the handle (capture is not
+    // allowed on the legacy default stream); events order it after / before `s`.
+    if (!B.stream) UTRI_HIP_TRY(hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking));
+    if (!B.ev) UTRI_HIP_TRY(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+    UTRI_HIP_TRY(hipEventRecord(B.ev, s));
+    UTRI_HIP_TRY(hipStreamWaitEvent(B.stream, B.ev, 0));
+    hipStream_t gs = B.stream;
+    const bool same = B.exec && B.nt == nt && B.k == k && B.worlds == worlds && B.exact == exact &&
+                      B.est == est && B.cvals == cv;
+    if (!same) {
+        if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
+        if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
+        // eager run first: sizes every scratch buffer, so capture records kernels only
+        UTRI_TRY(batch_sequence(g, dc, dord, nt, cv[0], k, worlds, sd, exact, est, gs));
+        UTRI_HIP_TRY(hipStreamSynchronize(gs));
+        UTRI_HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        int rc = batch_sequence(g, dc, dord, nt, cv[0], k, worlds, sd, exact, est, gs);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(gs, &gr);
+        if (rc != UTRI_OK) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+        UTRI_HIP_TRY(e);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(gr); UTRI_HIP_TRY(e); }
+        B.graph = gr;
+        B.exec = ex;
+        B.nt = nt;
+        B.k = k;
+        B.worlds = worlds;
+        B.exact = exact;
+        B.est = est;
+        B.cvals = cv;
+    }
+    // thresholds and seed are read from device buffers written above on `s`
+    UTRI_HIP_TRY(hipGraphLaunch(B.exec, gs));
+    UTRI_HIP_TRY(hipEventRecord(B.ev, gs));
+    UTRI_HIP_TRY(hipStreamWaitEvent(s, B.ev, 0));
+    // thresholds / seed were uploaded from host memory owned by this call
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!t_ok(t)) return UTRI_E_INVALID;
+    hipStream_t s = as_stream(hip_stream);
+    hipEvent_t e0, e1;
+    UTRI_HIP_TRY(hipEventCreate(&e0));
+    UTRI_HIP_TRY(hipEventCreate(&e1));
+    int64_t out[2];
+    float best = 1e30f;
+    int best_b = g->walk_blocks_per_cu;
+    for (int b : {1, 2, 3, 4, 6, 8}) {
+        g->walk_blocks_per_cu = b;
+        UTRI_TRY(count_impl(g, t, UTRI_PRUNED, out, s));  // warm-up
+        float tot = 0.f;
+        for (int r = 0; r < 3; r++) {
+            UTRI_HIP_TRY(hipEventRecord(e0, s));
+            UTRI_TRY(count_impl(g, t, UTRI_PRUNED, out, s));
+            UTRI_HIP_TRY(hipEventRecord(e1, s));
+            UTRI_HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            UTRI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        if (tot < best) { best = tot; best_b = b; }
+    }
+    g->walk_blocks_per_cu = best_b;
+    // sampler work-unit size
+    std::vector<double> tv{t};
+    double* est = nullptr;
+    const int32_t worlds = 64;
+    const int64_t k = 4096;
+    UTRI_HIP_TRY(hipMalloc(&est, sizeof(double) * worlds * 2));
+    float best_s = 1e30f;
+    int best_c = g->sample_chunk;
+    for (int c : {256, 1024, 4096}) {
+        g->sample_chunk = c;
+        int rc = utri_sample(g, tv.data(), 1, k, worlds, 12345, UTRI_SAMPLE_EDGE, est, hip_stream);
+        if (rc != UTRI_OK) { (void)hipFree(est); return rc; }
+        float tot = 0.f;
+        for (int r = 0; r < 3; r++) {
+            UTRI_HIP_TRY(hipEventRecord(e0, s));
+            rc = utri_sample(g, tv.data(), 1, k, worlds, 12345, UTRI_SAMPLE_EDGE, est, hip_stream);
+            UTRI_HIP_TRY(hipEventRecord(e1, s));
+            UTRI_HIP_TRY(hipEventSynchronize(e1));
+            if (rc != UTRI_OK) { (void)hipFree(est); return rc; }
+            float ms = 0.f;
+            UTRI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        if (tot < best_s) { best_s = tot; best_c = c; }
+    }
+    g->sample_chunk = best_c;
+    (void)hipFree(est);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{%s, \"walk_blocks_per_cu\": %d, \"sample_chunk\": %d}\n",
+                    cache_key(g).c_str(), g->walk_blocks_per_cu, g->sample_chunk);
+            fclose(f);
+        }
+    }
+    return UTRI_OK;
+}
+
+}  // extern "C"

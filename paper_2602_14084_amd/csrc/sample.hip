@@ -1,0 +1,164 @@
+// sample.hip -- edge-sampling estimator (Algorithms "Baseline Edge Sampling" and
+// "Improved Edge Local Search", Section 6.2), per-edge local counts, and the
+// histogram-to-count / estimate finalisation shared with the batch path.
+//
+// Local search of a sampled edge e = (a, b): nothing if |d_e| < c (Lemma 2); else the
+// Absolute-Edge-Order prefix (|d| >= c) of the shorter row is streamed and each
+// neighbour is looked up in the other row's hash table. That mirrors the improved
+// local search, whose cost is the pruned degree of the cheaper endpoint (Theorem 6.3).
+#include <algorithm>
+
+#include "walk_common.h"
+
+using namespace utri_dev;
+
+namespace {
+
+inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
+
+__global__ void k_symlen(const int64_t* __restrict__ off, const double* __restrict__ dd, int64_t n,
+                         double c, int32_t* __restrict__ len) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int64_t a = off[v], b = off[v + 1];
+    int64_t lo = a, hi = b;
+    if (c > 0.0) {
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (fabs(dd[mid]) >= c) lo = mid + 1; else hi = mid;
+        }
+    } else {
+        lo = b;
+    }
+    len[v] = (int32_t)(lo - a);
+}
+
+__global__ void __launch_bounds__(TPB) k_sample(SampleParams sp, SampleGraph G,
+                                                const int32_t* __restrict__ slen, int64_t units) {
+    __shared__ WaveLds lds[WPB];
+    const int wib = threadIdx.x / UTRI_WAVE;
+    WaveLds& L = lds[wib];
+    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
+    const int64_t W = (int64_t)gridDim.x * WPB;
+    const int64_t upw = (sp.k + sp.chunk - 1) / sp.chunk;
+    for (int64_t u = gw; u < units; u += W) {
+        const int32_t world = (int32_t)(u / upw);
+        const int64_t part = u % upw;
+        const int64_t i0 = part * sp.chunk;
+        const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
+        sample_unit(sp, G, slen, world, i0, i1, L);
+    }
+}
+
+// one wave per listed edge: out[i][j][0/1] = local counts at threshold j (original order)
+__global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double* __restrict__ cv,
+                                                    const int32_t* __restrict__ order, int nt,
+                                                    const int64_t* __restrict__ eids, int64_t k,
+                                                    int64_t* __restrict__ out) {
+    __shared__ unsigned long long hist[WPB][2][NB];
+    const int wib = threadIdx.x / UTRI_WAVE;
+    const int lane = utri_lane();
+    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
+    const int64_t W = (int64_t)gridDim.x * WPB;
+    for (int64_t q = gw; q < k; q += W) {
+        for (int t = lane; t < 2 * NB; t += UTRI_WAVE) hist[wib][t / NB][t % NB] = 0;
+        utri_wave_sync();
+        const int64_t e = eids[q];
+        const double de = G.e_d[e];
+        const int32_t a = G.inv[G.e_lo[e]], b = G.inv[G.e_hi[e]];
+        const int64_t la = G.s_off[a + 1] - G.s_off[a], lb = G.s_off[b + 1] - G.s_off[b];
+        const bool ax = (la < lb) || (la == lb && a < b);
+        const int32_t x = ax ? a : b, y = ax ? b : a;
+        const int64_t lx = ax ? la : lb;
+        const int64_t xoff = G.s_off[x], yoff = G.s_off[y], hoff = G.h_off[y];
+        const int lg = log2_size(G.h_off[y + 1] - hoff);
+        for (int64_t j = lane; j < lx; j += UTRI_WAVE) {
+            const int32_t w = G.s_adj[xoff + j];
+            const int64_t py = sym_lookup(G.h_slot, hoff, lg, w);
+            if (py >= 0) {
+                const double s = utri_tri_s(de, G.s_d[xoff + j], G.s_d[yoff + py]);
+                bool bal;
+                const int bin = utri_bin_of(s, cv, nt, bal);
+                if (bin > 0) atomicAdd(&hist[wib][bal ? 0 : 1][bin], 1ull);
+            }
+        }
+        utri_wave_sync();
+        // suffix sums: a triangle in bin k is classified at sorted thresholds 0..k-1
+        for (int js = lane; js < nt; js += UTRI_WAVE) {
+            unsigned long long cb = 0, cu = 0;
+            for (int bin = js + 1; bin <= nt; bin++) { cb += hist[wib][0][bin]; cu += hist[wib][1][bin]; }
+            const int jo = order[js];
+            out[(q * nt + jo) * 2] = (int64_t)cb;
+            out[(q * nt + jo) * 2 + 1] = (int64_t)cu;
+        }
+        utri_wave_sync();
+    }
+}
+
+// hist [rows][2][nt+1] -> counts [rows][nt][2] (threshold order given by `order`) and
+// est [rows][nt][2] = ((double)count * (double)m) / (3.0 * (double)k)
+__global__ void k_finalize(const unsigned long long* __restrict__ hist, int rows, int nt,
+                           const int32_t* __restrict__ order, int64_t m, int64_t k,
+                           int64_t* __restrict__ counts, double* __restrict__ est) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * nt * 2) return;
+    const int cls = (int)(t & 1);
+    const int js = (int)((t >> 1) % nt);
+    const int64_t r = (t >> 1) / nt;
+    const unsigned long long* h = hist + (r * 2 + cls) * (nt + 1);
+    unsigned long long c = 0;
+    for (int bin = js + 1; bin <= nt; bin++) c += h[bin];
+    const int jo = order ? order[js] : js;
+    const int64_t o = (r * nt + jo) * 2 + cls;
+    if (counts) counts[o] = (int64_t)c;
+    if (est) est[o] = ((double)c * (double)m) / (3.0 * (double)k);
+}
+
+}  // namespace
+
+int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen) {
+    void* p;
+    UTRI_TRY(utri_scratch(g, SCR_SLEN, sizeof(int32_t) * (size_t)(g->n + 1), &p));
+    *slen = (int32_t*)p;
+    if (g->n == 0) return UTRI_OK;
+    hipLaunchKernelGGL(k_symlen, dim3(blocks_for(g->n)), dim3(TPB), 0, s, g->s_off, g->s_d, g->n,
+                       c_rows, (int32_t*)p);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+static SampleGraph sample_graph(utri_graph* g) {
+    return SampleGraph{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d,
+                       g->h_off, g->h_slot};
+}
+
+int utri_sample_launch(utri_graph* g, const SampleParams& sp, const int32_t* slen, hipStream_t s) {
+    if (g->m == 0 || sp.k <= 0 || sp.worlds <= 0) return UTRI_OK;
+    const int64_t units = (int64_t)sp.worlds * ((sp.k + sp.chunk - 1) / sp.chunk);
+    const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * g->walk_blocks_per_cu,
+                                              (units + WPB - 1) / WPB);
+    hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(TPB), 0, s, sp, sample_graph(g), slen, units);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
+                           const int64_t* eids, int64_t k, int64_t* out, hipStream_t s) {
+    if (k <= 0) return UTRI_OK;
+    const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * 8, (k + WPB - 1) / WPB);
+    hipLaunchKernelGGL(k_edge_local, dim3(blocks), dim3(TPB), 0, s, sample_graph(g), cvals, order,
+                       nt, eids, k, out);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const int32_t* order,
+                         int64_t m, int64_t k, int64_t* counts_out, double* est_out,
+                         hipStream_t s) {
+    const int64_t tot = (int64_t)rows * nt * 2;
+    if (tot == 0) return UTRI_OK;
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(tot)), dim3(TPB), 0, s, hist, rows, nt, order,
+                       m, k > 0 ? k : 1, counts_out, est_out);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}

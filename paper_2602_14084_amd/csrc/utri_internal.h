@@ -1,0 +1,338 @@
+// utri_internal.h -- shared declarations of the HIP library (not part of the ABI).
+//
+// Data layout in HBM (all device memory, owned by the graph handle):
+//   canonical edges, edge-id order      e_lo/e_hi int32 [m], e_p/e_d f64 [m]
+//   vertex relabelling                  perm (new -> original) / inv int32 [n]
+//       new ids rank vertices by (degree, id): the Node Order of Section 4.
+//   symmetric rows, new ids             s_off int64 [n+1], s_adj int32 [2m],
+//       each row in Absolute Edge Order  s_d f64 [2m], s_eid int32 [2m]
+//       (|d| descending, then neighbour id ascending; Section 5), so the entries
+//       with |d| >= c of any row form a prefix.
+//   per-row open-addressing tables      h_off int64 [n+1], h_slot u64 [sum of sizes]
+//       slot = (neighbour << 32) | position in the row; size = pow2 >= 2*deg.
+//   oriented rows u -> v (v > u)        o_off int64 [n+1], o_adj int32 [m],
+//       same Absolute Edge Order         o_d f64 [m], o_eid int32 [m]
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "utri.h"
+
+#define UTRI_WAVE 64
+
+// ------------------------------------------------------------------ error plumbing
+
+#define UTRI_HIP_TRY(expr)                                 \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) {                            \
+            utri_note_hip_error(_e, #expr, __FILE__, __LINE__); \
+            return (_e == hipErrorOutOfMemory) ? UTRI_E_NOMEM : UTRI_E_HIP; \
+        }                                                  \
+    } while (0)
+
+#define UTRI_TRY(expr)                 \
+    do {                               \
+        int _rc = (expr);              \
+        if (_rc != UTRI_OK) return _rc; \
+    } while (0)
+
+void utri_note_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+// device error flag bits
+enum : uint32_t {
+    UTRI_FLAG_BAD_ID = 1u,
+    UTRI_FLAG_BAD_P = 2u,
+    UTRI_FLAG_CONFLICT = 4u,
+};
+
+// scratch buffers kept by a handle between calls (grown on demand)
+enum UtriScratch {
+    SCR_TEMP = 0,     // rocPRIM temporary storage
+    SCR_LEN,          // int32 [n] row prefix lengths at c (oriented)
+    SCR_SLEN,         // int32 [n] row prefix lengths at c (symmetric)
+    SCR_ICNT,         // int32 [n] items per vertex
+    SCR_IOFF,         // int64 [n] item offsets
+    SCR_ITEMS,        // int64 [items]
+    SCR_NITEMS,       // int64 [4] item count and friends
+    SCR_ACC,          // u64 accumulators of a query
+    SCR_CVALS,        // f64 [64] sorted thresholds
+    SCR_ICNT2,        // int64 [items][2] per-item counts (enumeration)
+    SCR_IOFF2,        // int64 [items][2] per-item offsets (enumeration)
+    SCR_SORT_A,       // enumeration sort buffers
+    SCR_SORT_B,
+    SCR_SORT_C,
+    SCR_SORT_D,
+    SCR_HIST,         // u64 [worlds][2][nt+1]
+    SCR_BATCH_T,      // f64 [64] thresholds of the captured batch
+    SCR_ORDER,        // int32 [64] original position of each sorted threshold
+    SCR_OUT,          // int64 small device results
+    SCR_SEED,         // u64 seed of the captured batch
+    SCR_HIST2,        // u64 walk histogram of the batch
+    SCR_COUNT
+};
+
+struct UtriBatchGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<double> cvals;
+    int nt = 0;
+    int64_t k = 0;
+    int32_t worlds = 0;
+    int64_t* exact = nullptr;
+    double* est = nullptr;
+};
+
+struct utri_graph {
+    int device = 0;
+    int num_cu = 256;
+    int64_t n = 0, m = 0;
+    int64_t self_loops = 0, dups = 0, max_deg = 0, max_out = 0;
+
+    int32_t *e_lo = nullptr, *e_hi = nullptr;
+    double *e_p = nullptr, *e_d = nullptr;
+    int32_t *perm = nullptr, *inv = nullptr;
+    int32_t* deg_new = nullptr;  // degree of each new id (ascending)
+
+    int64_t* s_off = nullptr;
+    int32_t* s_adj = nullptr;
+    double* s_d = nullptr;
+    int32_t* s_eid = nullptr;
+    int32_t* s_row = nullptr;    // row of each symmetric entry
+
+    int64_t* h_off = nullptr;
+    uint64_t* h_slot = nullptr;
+    int64_t h_total = 0;
+
+    int64_t* o_off = nullptr;
+    int32_t* o_adj = nullptr;
+    double* o_d = nullptr;
+    int32_t* o_eid = nullptr;
+
+    uint32_t* d_flags = nullptr;
+
+    void* scr[SCR_COUNT] = {};
+    size_t scr_bytes[SCR_COUNT] = {};
+
+    // launch shape (set by the autotuner, else defaults)
+    int walk_blocks_per_cu = 8;
+    int sample_chunk = 2048;
+
+    UtriBatchGraph batch;
+};
+
+int utri_scratch(utri_graph* g, int slot, size_t bytes, void** out);
+int utri_build_rows(utri_graph* g, hipStream_t s);
+
+// ------------------------------------------------------------------ device helpers
+
+// Canonical FP64 decision, the library's own copy:
+//   d = 1.0 - 2.0*p, c = 2.0*t - 1.0, three d sorted ascending, s = (x*y)*z.
+__host__ __device__ inline double utri_d_of_p(double p) { return 1.0 - 2.0 * p; }
+__host__ __device__ inline double utri_c_of_t(double t) { return 2.0 * t - 1.0; }
+
+__device__ inline double utri_tri_s(double a, double b, double c) {
+    double lo = fmin(a, b), hi = fmax(a, b);
+    double x = fmin(lo, c);          // smallest
+    double z = fmax(hi, c);          // largest
+    double y = fmax(lo, fmin(hi, c));  // middle
+    double xy = __dmul_rn(x, y);
+    return __dmul_rn(xy, z);
+}
+
+// nearest multiple of 2^-62 (ties to even) of |x| <= 1, as an integer
+__device__ inline int64_t utri_fix62(double x) {
+    return (int64_t)rint(x * 0x1p62);
+}
+
+// correctly rounded conversion of a two's complement 128-bit integer (hi:lo) to double
+__host__ __device__ inline double utri_u64_to_double_rn(uint64_t v) {
+    // the product is exact and the single addition rounds once
+    double h = (double)(uint32_t)(v >> 32) * 4294967296.0;
+    double l = (double)(uint32_t)(v & 0xFFFFFFFFull);
+    return h + l;
+}
+
+__host__ __device__ inline double utri_i128_to_double(int64_t hi, uint64_t lo) {
+    bool neg = hi < 0;
+    uint64_t uhi = (uint64_t)hi, ulo = lo;
+    if (neg) {
+        ulo = ~ulo + 1ull;
+        uhi = ~uhi + (ulo == 0 ? 1ull : 0ull);
+    }
+    double r;
+    if (uhi == 0) {
+        r = utri_u64_to_double_rn(ulo);
+    } else {
+        int lz = 0;
+        while (!((uhi << lz) & 0x8000000000000000ull)) lz++;
+        int sh = 64 - lz;  // shift right by sh bits to fit 64 bits
+        uint64_t v = (sh == 64) ? uhi : ((uhi << (64 - sh)) | (ulo >> sh));
+        uint64_t lost = (sh == 64) ? ulo : (ulo << (64 - sh));
+        if (lost) v |= 1ull;  // sticky bit below the rounding position (v has 64 significant bits)
+        r = utri_u64_to_double_rn(v);
+        r = ldexp(r, sh);
+    }
+    return neg ? -r : r;
+}
+
+__device__ inline uint32_t utri_hash32(int32_t key, int lg) {
+    return ((uint32_t)key * 0x9E3779B1u) >> (32 - lg);
+}
+
+__device__ inline void utri_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int utri_lane() { return (int)(threadIdx.x & (UTRI_WAVE - 1)); }
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ inline int64_t utri_wave_incl_scan(int64_t v) {
+    const int lane = utri_lane();
+#pragma unroll
+    for (int d = 1; d < UTRI_WAVE; d <<= 1) {
+        int64_t o = __shfl_up(v, d, UTRI_WAVE);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ inline uint64_t utri_wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int d = UTRI_WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, UTRI_WAVE);
+    return v;
+}
+
+// 128-bit sum over the wave of (hi:lo) pairs, exact modulo 2^128
+__device__ inline void utri_wave_sum_u128(uint64_t& lo, uint64_t& hi) {
+#pragma unroll
+    for (int d = UTRI_WAVE / 2; d >= 1; d >>= 1) {
+        uint64_t olo = __shfl_xor(lo, d, UTRI_WAVE);
+        uint64_t ohi = __shfl_xor(hi, d, UTRI_WAVE);
+        uint64_t s = lo + olo;
+        hi = hi + ohi + (s < lo ? 1ull : 0ull);
+        lo = s;
+    }
+}
+
+// exact 128-bit atomic accumulation into (acc[0] = lo, acc[1] = hi)
+__device__ inline void utri_atomic_add_u128(unsigned long long* acc, uint64_t lo, uint64_t hi) {
+    unsigned long long old = atomicAdd(&acc[0], (unsigned long long)lo);
+    uint64_t carry = ((uint64_t)old + lo < (uint64_t)old) ? 1ull : 0ull;
+    if (hi + carry) atomicAdd(&acc[1], (unsigned long long)(hi + carry));
+}
+
+// Philox4x32-10 block (Salmon, Moraes, Dror, Shaw, SC'11): multipliers 0xD2511F53 and
+// 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85, ten rounds.
+__device__ inline void utri_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                   uint32_t k1, uint32_t* out) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// edge drawn by sample i of world w
+__device__ inline int64_t utri_sample_edge(uint64_t seed, uint32_t world, uint64_t i, int64_t m) {
+    uint32_t x[4];
+    utri_philox((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u, (uint32_t)seed ^ world,
+                (uint32_t)(seed >> 32), x);
+    uint64_t x64 = ((uint64_t)x[1] << 32) | (uint64_t)x[0];
+    return (int64_t)__umul64hi(x64, (uint64_t)m);
+}
+
+// number of thresholds c_j (sorted ascending, nt of them) that the value s passes:
+// for s <= 0, #{j : c_j <= -s} (balanced at every j below it); for s > 0, #{j : c_j < s}.
+__device__ inline int utri_bin_of(double s, const double* cv, int nt, bool& bal) {
+    bal = (s <= 0.0);
+    double key = bal ? -s : s;
+    int lo = 0, hi = nt;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        bool pass = bal ? (cv[mid] <= key) : (cv[mid] < key);
+        if (pass) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ kernels (host launchers)
+
+// per-query preparation of the oriented walk
+int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int64_t** items,
+                      int64_t** n_items_dev, int32_t** len);
+
+enum WalkMode { WALK_COUNT = 0, WALK_HIST = 1, WALK_EXPECTED = 2, WALK_ENUM_COUNT = 3, WALK_ENUM_FILL = 4 };
+
+struct WalkParams {
+    double c = 0.0;          // decision threshold (COUNT / ENUM)
+    int lemma3 = 0;
+    double c_l3 = 0.0;       // c * (1 - 2^-50) for the Lemma-3 cut
+    const double* cvals = nullptr;  // HIST: sorted thresholds
+    int nt = 0;
+    unsigned long long* acc = nullptr;  // COUNT [2], HIST [2][nt+1], EXPECTED [3]
+    int64_t* cnt_b = nullptr;           // ENUM_COUNT [items] balanced per item
+    int64_t* cnt_u = nullptr;           // ENUM_COUNT [items] unbalanced per item
+    const int64_t* off_b = nullptr;     // ENUM_FILL [items] output offsets
+    const int64_t* off_u = nullptr;
+    int32_t* out_bal = nullptr;
+    int32_t* out_unbal = nullptr;
+    int which = UTRI_BOTH;
+};
+
+int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_t* items,
+                     const int64_t* n_items_dev, const int32_t* len, int64_t n_items_host_bound,
+                     hipStream_t s);
+
+struct SampleParams {
+    const double* cvals = nullptr;  // sorted thresholds, nt of them
+    int nt = 0;
+    double cmin = 0.0;
+    uint64_t seed = 0;
+    const uint64_t* seed_dev = nullptr;  // if set, the seed is read from device memory
+    int64_t k = 0;
+    int32_t worlds = 0;
+    int chunk = 2048;               // samples per work unit (multiple of 64)
+    unsigned long long* hist = nullptr;  // [worlds][2][nt+1]
+};
+
+int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen);
+int utri_sample_launch(utri_graph* g, const SampleParams& sp, const int32_t* slen, hipStream_t s);
+int utri_batch_launch(utri_graph* g, const WalkParams& wp, const int64_t* items,
+                      const int64_t* n_items_dev, const int32_t* len, int64_t n_items_bound,
+                      const SampleParams& sp, const int32_t* slen, hipStream_t s);
+int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const int32_t* order,
+                         int64_t m, int64_t k, int64_t* counts_out, double* est_out,
+                         hipStream_t s);
+int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
+                           const int64_t* eids, int64_t k, int64_t* out, hipStream_t s);
+int utri_walk_items_bound(utri_graph* g);
+int utri_grad_launch(utri_graph* g, double* grad, hipStream_t s);
+
+// generic helpers
+int utri_fill_u64(void* p, uint64_t v, int64_t count, hipStream_t s);
+int utri_exclusive_scan_i32_to_i64(utri_graph* g, const int32_t* in, int64_t* out, int64_t n,
+                                   hipStream_t s);
+int utri_exclusive_scan_i64(utri_graph* g, const int64_t* in, int64_t* out, int64_t n,
+                            hipStream_t s);
+// graph-capture-safe exclusive scans (kernels only); *total optional, device memory
+int utri_scan_i32(utri_graph* g, const int32_t* in, int64_t* out, int64_t n, int64_t* total,
+                  hipStream_t s);
+int utri_scan_i64(utri_graph* g, const int64_t* in, int64_t* out, int64_t n, int64_t* total,
+                  hipStream_t s);
+int utri_load_internal(const int64_t* src, const int64_t* dst, const double* p, int64_t m_in,
+                       int64_t n, int ptr_kind, hipStream_t s, utri_graph** out);
+int utri_set_p_internal(utri_graph* g, const double* p, int ptr_kind, hipStream_t s);
+void utri_free_graph_internal(utri_graph* g);

@@ -1,0 +1,140 @@
+// walk_common.h -- per-wave LDS layout and the edge-sampling work unit shared by the
+// sampler kernels and the fused batch kernel.
+#pragma once
+
+#include "utri_internal.h"
+
+namespace utri_dev {
+
+constexpr int TPB = 256;
+constexpr int WPB = TPB / UTRI_WAVE;
+constexpr int CAP = 512;       // hash-side entries per walk item
+constexpr int HS = 2 * CAP;    // LDS table slots (load factor <= 1/2)
+constexpr int NB = 65;         // histogram bins (nt + 1 <= 65)
+
+struct WaveLds {
+    int32_t key[HS];
+    uint16_t pos[HS];
+    int32_t end[UTRI_WAVE];       // inclusive prefix of segment lengths
+    int64_t xoff[UTRI_WAVE];      // start of the streamed row of each segment
+    double dseg[UTRI_WAVE];       // d of the segment's own edge
+    int32_t vseg[UTRI_WAVE];      // walk: v of the segment
+    int64_t yoff[UTRI_WAVE];      // sampler: start of the probe-side row
+    int64_t hoff[UTRI_WAVE];      // sampler: start of the probe-side table
+    int32_t hlg[UTRI_WAVE];       // sampler: log2 size of the probe-side table
+    unsigned long long hist[2][NB];   // walk histogram (per wave, whole launch)
+    unsigned long long shist[2][NB];  // sampler histogram (per work unit)
+};
+
+__device__ inline int seg_search(const int32_t* end, int f) {
+    // smallest index i with end[i] > f (end is non-decreasing and end[63] > f)
+    int lo = 0, hi = UTRI_WAVE - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (end[mid] > f) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+struct SampleGraph {
+    int64_t m;
+    const int32_t* e_lo;
+    const int32_t* e_hi;
+    const double* e_d;
+    const int32_t* inv;
+    const int64_t* s_off;
+    const int32_t* s_adj;
+    const double* s_d;
+    const int64_t* h_off;
+    const uint64_t* h_slot;
+};
+
+// position of w in the symmetric row whose table starts at hoff with 2^lg slots, or -1
+__device__ inline int64_t sym_lookup(const uint64_t* __restrict__ h_slot, int64_t hoff, int lg,
+                                     int32_t w) {
+    const uint32_t mask = (1u << lg) - 1u;
+    uint32_t h = utri_hash32(w, lg);
+    for (;;) {
+        const uint64_t sl = h_slot[hoff + h];
+        if (sl == ~0ull) return -1;
+        if ((int32_t)(sl >> 32) == w) return (int64_t)(uint32_t)(sl & 0xFFFFFFFFull);
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ inline int log2_size(int64_t size) {
+    int lg = 0;
+    while ((1ll << lg) < size) lg++;
+    return lg;
+}
+
+// One work unit of the edge-sampling estimator: samples [i_begin, i_end) of `world`.
+// Each sampled edge e = (a, b) with |d_e| >= cmin streams the Absolute-Edge-Order
+// prefix (|d| >= cmin) of its shorter row and probes the other row's hash table; the
+// triangles found are classified and binned by threshold into the wave's histogram,
+// which is added to hist[world][2][nt+1] at the end of the unit.
+__device__ inline void sample_unit(const SampleParams& sp, const SampleGraph& G,
+                                   const int32_t* __restrict__ slen, int32_t world,
+                                   int64_t i_begin, int64_t i_end, WaveLds& L) {
+    const int lane = utri_lane();
+    for (int q = lane; q < 2 * NB; q += UTRI_WAVE) L.shist[q / NB][q % NB] = 0;
+    utri_wave_sync();
+    for (int64_t i0 = i_begin; i0 < i_end; i0 += UTRI_WAVE) {
+        const int64_t i = i0 + lane;
+        int work = 0;
+        int64_t xoff = 0, yoff = 0, hoff = 0;
+        int lg = 0;
+        double de = 0.0;
+        if (i < i_end) {
+            const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
+            const int64_t e = utri_sample_edge(seed, (uint32_t)world, (uint64_t)i, G.m);
+            de = G.e_d[e];
+            if (fabs(de) >= sp.cmin) {
+                const int32_t a = G.inv[G.e_lo[e]], b = G.inv[G.e_hi[e]];
+                const int la = slen[a], lb = slen[b];
+                const bool ax = (la < lb) || (la == lb && a < b);
+                const int32_t x = ax ? a : b, y = ax ? b : a;
+                work = ax ? la : lb;
+                xoff = G.s_off[x];
+                yoff = G.s_off[y];
+                hoff = G.h_off[y];
+                lg = log2_size(G.h_off[y + 1] - hoff);
+            }
+        }
+        const int incl = (int)utri_wave_incl_scan((int64_t)work);
+        const int total = __shfl(incl, UTRI_WAVE - 1, UTRI_WAVE);
+        L.end[lane] = incl;
+        L.xoff[lane] = xoff;
+        L.yoff[lane] = yoff;
+        L.hoff[lane] = hoff;
+        L.hlg[lane] = lg;
+        L.dseg[lane] = de;
+        utri_wave_sync();
+        for (int f0 = 0; f0 < total; f0 += UTRI_WAVE) {
+            const int f = f0 + lane;
+            if (f < total) {
+                const int sg = seg_search(L.end, f);
+                const int start = sg ? L.end[sg - 1] : 0;
+                const int64_t px = L.xoff[sg] + (f - start);
+                const int32_t w = G.s_adj[px];
+                const int64_t py = sym_lookup(G.h_slot, L.hoff[sg], L.hlg[sg], w);
+                if (py >= 0) {
+                    const double s = utri_tri_s(L.dseg[sg], G.s_d[px], G.s_d[L.yoff[sg] + py]);
+                    bool bal;
+                    const int bin = utri_bin_of(s, sp.cvals, sp.nt, bal);
+                    if (bin > 0) atomicAdd(&L.shist[bal ? 0 : 1][bin], 1ull);
+                }
+            }
+        }
+        utri_wave_sync();
+    }
+    for (int q = lane; q < 2 * NB; q += UTRI_WAVE) {
+        const int cls = q / NB, bin = q % NB;
+        const unsigned long long v = L.shist[cls][bin];
+        if (v && bin <= sp.nt)
+            atomicAdd(&sp.hist[((int64_t)world * 2 + cls) * (sp.nt + 1) + bin], v);
+    }
+    utri_wave_sync();
+}
+
+}  // namespace utri_dev

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Counts and enumerated sets are compared bit for bit; the expected count and the
+gradient use the same fixed-point rule on both sides and are compared for exact
+equality (the 1e-12 relative bound on E is met with room to spare); sampler
+estimates replay the same Philox draws and are compared exactly. Sizes span several
+work items (rows cut into 512-entry chunks, many 64-lane strips) and ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_14084_amd import inputs, utri
+
+pytestmark = pytest.mark.gpu
+
+TS = [0.5, 0.5625, 0.6, 0.75, 0.8, 0.9, 0.9375, 1.0]
+METHODS = [utri.UTRI_PLAIN, utri.UTRI_PRUNED, utri.UTRI_PRUNED_L3]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_graph(n, lo, hi, p, device=True):
+    if device:
+        d = torch.device("cuda")
+        return utri.Graph(torch.from_numpy(np.asarray(lo)).to(d), torch.from_numpy(np.asarray(hi)).to(d),
+                          torch.from_numpy(np.asarray(p, dtype=np.float64)).to(d), n)
+    return utri.Graph(lo, hi, p, n)
+
+
+def cases():
+    out = []
+    for seed, (n, dens) in enumerate([(9, 1.0), (14, 0.7), (40, 0.4), (120, 0.15)]):
+        out.append(("er%d" % seed,) + inputs.random_graph(n, dens, 300 + seed))
+    out.append(("chunglu",) + inputs.chung_lu_graph())
+    out.append(("chunglu_dense",) + inputs.chung_lu_graph(400, 2.1, 12000.0, 5))
+    out.append(("rmat12",) + inputs.rmat_graph(12, seed=3))
+    return out
+
+
+CASES = cases()
+
+
+@pytest.mark.parametrize("dist", ["uniform", "dyadic16", "beta0505", "certain", "tri", "half", "bimodal"])
+def test_count_all_methods_match_oracle(dist):
+    for name, n, lo, hi in CASES:
+        p = inputs.draw_p(lo.shape[0], dist, 17)
+        og = oracle.load(n, lo, hi, p)
+        want = og.count_multi(TS)
+        say("count", name, dist, "n", n, "m", lo.shape[0])
+        g = gpu_graph(n, lo, hi, p)
+        for j, t in enumerate(TS):
+            for method in METHODS:
+                assert g.count(t, method) == tuple(want[j]), (name, dist, t, method)
+        got = g.count_batch(TS)
+        assert np.array_equal(got, want), (name, dist)
+
+
+def test_count_which_selector():
+    name, n, lo, hi = CASES[4]
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = gpu_graph(n, lo, hi, p)
+    nb, nu = g.count(0.6)
+    assert g.count(0.6, which=utri.UTRI_BAL) == (nb, 0)
+    assert g.count(0.6, which=utri.UTRI_UNBAL) == (0, nu)
+
+
+def test_count_rmat_multi_tile():
+    n, lo, hi = inputs.rmat_graph(16, seed=7)
+    for dist in ["beta22", "bimodal"]:
+        p = inputs.draw_p(lo.shape[0], dist, 2)
+        og = oracle.load(n, lo, hi, p)
+        ts = [0.5, 0.7, 0.8, 0.9]
+        want = og.count_multi(ts)
+        say("rmat16", dist, "m", lo.shape[0])
+        g = gpu_graph(n, lo, hi, p)
+        for j, t in enumerate(ts):
+            for method in METHODS:
+                assert g.count(t, method) == tuple(want[j]), (dist, t, method)
+        assert np.array_equal(g.count_batch(ts), want)
+
+
+def test_load_canonicalises_on_device_and_host():
+    n, lo, hi = inputs.chung_lu_graph(700, 2.5, 6000.0, 8)
+    p = inputs.draw_p(lo.shape[0], "uniform", 9)
+    s, d, pp = inputs.dirty_edges(lo, hi, p, seed=10, n=n)
+    for device in (True, False):
+        say("load", "device" if device else "host")
+        g = gpu_graph(n, s, d, pp, device)
+        assert g.m == lo.shape[0] and g.self_loops == 5 and g.dups == int(lo.shape[0] * 0.1)
+        elo, ehi, ep = g.edges()
+        assert np.array_equal(elo.numpy(), lo) and np.array_equal(ehi.numpy(), hi)
+        assert np.array_equal(ep.numpy(), p)
+
+
+def test_enumerate_matches_oracle():
+    for name, n, lo, hi in CASES[3:]:
+        for dist in ["uniform", "dyadic16"]:
+            p = inputs.draw_p(lo.shape[0], dist, 23)
+            og = oracle.load(n, lo, hi, p)
+            g = gpu_graph(n, lo, hi, p)
+            for t in [0.5, 0.6, 0.75, 0.9375]:
+                ob, ou = og.enumerate(t)
+                for method in METHODS:
+                    say("enumerate", name, dist, t, method)
+                    bal, unb = g.enumerate(t, method)
+                    assert np.array_equal(bal.cpu().numpy(), ob), (name, dist, t, method)
+                    assert np.array_equal(unb.cpu().numpy(), ou), (name, dist, t, method)
+                # unsorted output is the same set in a deterministic order
+                b1, _ = g.enumerate(t, sorted=False)
+                b2, _ = g.enumerate(t, sorted=False)
+                assert torch.equal(b1, b2)
+                assert np.array_equal(np.array(sorted(map(tuple, b1.cpu().numpy())), dtype=np.int32).reshape(-1, 3), ob)
+
+
+def test_enumerate_which_and_capacity():
+    name, n, lo, hi = CASES[4]
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    og = oracle.load(n, lo, hi, p)
+    ob, ou = og.enumerate(0.6)
+    g = gpu_graph(n, lo, hi, p)
+    bal, unb = g.enumerate(0.6, which=utri.UTRI_BAL)
+    assert np.array_equal(bal.cpu().numpy(), ob) and unb.shape[0] == 0
+    with pytest.raises(utri.UtriError) as ei:
+        utri.utri_enumerate(g.handle, 0.6, cap=(ob.shape[0] - 1, ou.shape[0]))
+    assert ei.value.code == utri.UTRI_E_CAPACITY
+
+
+def test_expected_matches_oracle_exactly():
+    for name, n, lo, hi in CASES:
+        for dist in ["uniform", "dyadic16", "half", "uniform_05_95"]:
+            p = inputs.draw_p(lo.shape[0], dist, 31)
+            og = oracle.load(n, lo, hi, p)
+            E0, T, _ = og.expected()
+            say("expected", name, dist)
+            g = gpu_graph(n, lo, hi, p)
+            E = g.expected()
+            assert E == E0, (name, dist, E, E0)
+            if dist == "half":
+                assert E == T / 2
+
+
+def test_grad_matches_oracle_exactly():
+    for name, n, lo, hi in CASES:
+        for dist in ["uniform", "dyadic16"]:
+            p = inputs.draw_p(lo.shape[0], dist, 37)
+            og = oracle.load(n, lo, hi, p)
+            say("grad", name, dist)
+            g = gpu_graph(n, lo, hi, p)
+            got = g.expected_grad().cpu().numpy()
+            assert np.array_equal(got, og.grad()), name
+
+
+def test_autograd_function_and_set_p():
+    n, lo, hi = inputs.chung_lu_graph(500, 2.5, 4000.0, 12)
+    p0 = inputs.draw_p(lo.shape[0], "uniform", 1)
+    p1 = inputs.draw_p(lo.shape[0], "uniform_05_95", 2)
+    g = gpu_graph(n, lo, hi, p0)
+    pt = torch.from_numpy(p1).cuda().requires_grad_(True)
+    E = utri.expected_balanced(pt, g)
+    E.backward()
+    og = oracle.load(n, lo, hi, p1)
+    assert E.item() == og.expected()[0]
+    assert np.array_equal(pt.grad.cpu().numpy(), og.grad())
+    # the graph now carries p1 for every query
+    assert g.count(0.6) == og.count(0.6)
+    with pytest.raises(utri.UtriError):
+        g.set_p(np.full(lo.shape[0], np.nan))
+    assert g.count(0.6) == og.count(0.6)
+
+
+def test_edge_local_matches_oracle():
+    n, lo, hi = inputs.rmat_graph(13, seed=5)
+    p = inputs.draw_p(lo.shape[0], "beta22", 6)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    ts = [0.9, 0.5, 0.7]
+    eids = np.random.default_rng(0).integers(0, lo.shape[0], 3000)
+    say("edge_local", "rmat13")
+    got = g.edge_local(ts, eids).cpu().numpy()
+    assert np.array_equal(got, og.edge_local(ts, eids))
+    allg = g.edge_local(ts, np.arange(lo.shape[0])).cpu().numpy().sum(axis=0)
+    want = og.count_multi(ts)
+    assert np.array_equal(allg, 3 * want)
+    with pytest.raises(utri.UtriError):
+        g.edge_local(ts, np.array([0, lo.shape[0]]))
+
+
+def test_sampler_replays_oracle_exactly():
+    for name, n, lo, hi in [CASES[4], ("rmat12",) + inputs.rmat_graph(12, seed=3)]:
+        p = inputs.draw_p(lo.shape[0], "uniform", 41)
+        og = oracle.load(n, lo, hi, p)
+        g = gpu_graph(n, lo, hi, p)
+        for ts, k, W, seed in [([0.6], 777, 5, 1), ([0.8, 0.5, 0.7], 2500, 33, 0xDEADBEEF12345)]:
+            say("sample", name, ts, k, W)
+            est = g.sample(ts, k, W, seed).cpu().numpy()
+            oest, _ = og.sample(ts, k, W, seed)
+            assert np.array_equal(est, oest), (name, ts)
+
+
+def test_batch_eager_and_graph_replays():
+    n, lo, hi = inputs.rmat_graph(13, seed=9)
+    p = inputs.draw_p(lo.shape[0], "beta22", 2)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    ts = [0.5 + 0.0075 * j for j in range(64)]
+    k, W, seed = 600, 16, 77
+    want_exact = og.count_multi(ts)
+    want_est, _ = og.sample(ts, k, W, seed)
+    say("batch eager")
+    ex, es = g.batch(ts, k, W, seed, use_graph=False)
+    assert np.array_equal(ex.cpu().numpy(), want_exact)
+    assert np.array_equal(es.cpu().numpy(), want_est)
+    ex2 = torch.empty_like(ex)
+    es2 = torch.empty_like(es)
+    side = torch.cuda.Stream()
+    for rep in range(4):
+        say("batch graph replay", rep)
+        ex2.fill_(-1)
+        es2.fill_(-1.0)
+        with torch.cuda.stream(side):
+            g.batch(ts, k, W, seed, use_graph=True, exact=ex2, est=es2)
+        torch.cuda.synchronize()
+        assert np.array_equal(ex2.cpu().numpy(), want_exact), rep
+        assert np.array_equal(es2.cpu().numpy(), want_est), rep
+        # eager work between replays
+        g.count(0.7)
+        g.count(0.8)
+    # a new seed is read from device memory by the same captured graph
+    want_est2, _ = og.sample(ts, k, W, seed + 1)
+    with torch.cuda.stream(side):
+        g.batch(ts, k, W, seed + 1, use_graph=True, exact=ex2, est=es2)
+    torch.cuda.synchronize()
+    assert np.array_equal(es2.cpu().numpy(), want_est2)
+
+
+def test_relabel_invariance_and_determinism():
+    n, lo, hi = inputs.rmat_graph(12, seed=11)
+    p = inputs.draw_p(lo.shape[0], "uniform", 3)
+    g = gpu_graph(n, lo, hi, p)
+    perm = np.random.default_rng(1).permutation(n)
+    g2 = gpu_graph(n, perm[lo], perm[hi], p)
+    for t in [0.5, 0.6, 0.8]:
+        assert g.count(t) == g2.count(t) == g.count(t)
+    assert g.expected() == g2.expected()
+    b1, _ = g.enumerate(0.6)
+    b2, _ = g2.enumerate(0.6)
+    inv = np.argsort(perm)
+    back = np.sort(inv[b2.cpu().numpy()], axis=1)
+    assert sorted(map(tuple, back)) == [tuple(r) for r in b1.cpu().numpy()]
+
+
+def test_error_paths():
+    lo = np.array([0, 0, 1], np.int64)
+    hi = np.array([1, 2, 2], np.int64)
+    for p, code in [([0.1, np.nan, 0.2], utri.UTRI_E_INVALID), ([0.1, 1.5, 0.2], utri.UTRI_E_INVALID)]:
+        with pytest.raises(utri.UtriError) as ei:
+            gpu_graph(3, lo, hi, np.array(p))
+        assert ei.value.code == code
+    with pytest.raises(utri.UtriError) as ei:
+        gpu_graph(3, np.array([0, 1, 1]), np.array([1, 0, 2]), np.array([0.1, 0.2, 0.3]))
+    assert ei.value.code == utri.UTRI_E_CONFLICT
+    with pytest.raises(utri.UtriError) as ei:
+        gpu_graph(3, np.array([0, 1]), np.array([1, 3]), np.array([0.1, 0.2]))
+    assert ei.value.code == utri.UTRI_E_INVALID
+    g = gpu_graph(3, lo, hi, np.array([0.1, 0.2, 0.3]))
+    for t in [0.4999, 1.01, float("nan")]:
+        with pytest.raises(utri.UtriError):
+            g.count(t)
+    assert g.count(0.5) in [(1, 0), (0, 1)]
+    # the handle stays usable after errors; an empty graph works too
+    e = gpu_graph(5, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0))
+    assert e.m == 0 and e.count(0.6) == (0, 0) and e.expected() == 0.0
