@@ -183,6 +183,26 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
  */
 int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream);
 
+/*
+ * Work figures of one counting walk at t (the units the cost analysis of Theorem 5.1,
+ * Section 5, sums over): out (host int64 [5]) =
+ *   [0] m_c: oriented edges kept (sum of the kept source-row prefixes),
+ *   [1] sum over kept oriented edges u -> v of the kept target-row length of v,
+ *   [2] candidate triangles (target-row entries found in the source row),
+ *   [3] target-row entries actually streamed (rows longer than one work item are
+ *       streamed once per item),
+ *   [4] work items. Waits for the stream.
+ */
+int utri_walk_stats(utri_graph* g, double t, int method, int64_t out[5], void* hip_stream);
+
+/*
+ * Event timing of the counting walk kernel launched by utri_count, recorded with HIP
+ * events on the stream the kernel runs on. enable = 1 resets and starts recording,
+ * 0 stops, any other value only reads. *ms and *launches (either may be NULL) return
+ * the accumulated kernel time and the number of timed launches.
+ */
+int utri_timing(utri_graph* g, int enable, double* ms, int64_t* launches);
+
 /* Human-readable text for a status code. */
 const char* utri_strerror(int code);
 

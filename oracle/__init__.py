@@ -40,6 +40,7 @@ def _load():
     lib.orc_edges.argtypes = [vp, _i32p, _i32p, _f64p]
     lib.orc_count.argtypes = [vp, C.c_double, _i64p]
     lib.orc_count_multi.argtypes = [vp, _f64p, C.c_int, _i64p]
+    lib.orc_count_vertices.argtypes = [vp, C.c_double, _i64p, C.c_int64, _i64p]
     lib.orc_enumerate.argtypes = [vp, C.c_double, _i32p, C.c_int64, _i32p, C.c_int64, _i64p]
     lib.orc_expected.argtypes = [vp, _f64p, _i64p, _u64p, _i64p]
     lib.orc_grad.argtypes = [vp, _i64p, C.c_int64, _f64p]
@@ -104,6 +105,16 @@ class OracleGraph:
         rc = self._lib.orc_count(self._h, float(t), _p(out, _i64p))
         if rc != OK:
             raise OracleError(rc, "count")
+        return int(out[0]), int(out[1])
+
+    def count_vertices(self, t, us):
+        """Counts of the triangles whose lowest-ranked vertex is in `us`."""
+        us = np.ascontiguousarray(us, dtype=np.int64)
+        out = np.zeros(2, np.int64)
+        rc = self._lib.orc_count_vertices(self._h, float(t), _p(us, _i64p), int(us.shape[0]),
+                                          _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "count_vertices")
         return int(out[0]), int(out[1])
 
     def count_multi(self, ts):

@@ -318,18 +318,28 @@ void orc_edges(const orc_graph* g, int32_t* lo, int32_t* hi, double* p) {
 typedef void (*orc_visit_fn)(void* ctx, int tid, int32_t u, int32_t v, int32_t w,
                              int32_t euv, int32_t euw, int32_t evw);
 
+static int orc_node_iterate_list(const orc_graph* g, const int64_t* list, int64_t nlist,
+                                 orc_visit_fn fn, void* ctx);
+
 static int orc_node_iterate(const orc_graph* g, orc_visit_fn fn, void* ctx, int nthreads_hint) {
+    (void)nthreads_hint;
+    return orc_node_iterate_list(g, NULL, g->n, fn, ctx);
+}
+
+/* Node iterator over the listed vertices (all vertices when list is NULL). */
+static int orc_node_iterate_list(const orc_graph* g, const int64_t* list, int64_t nlist,
+                                 orc_visit_fn fn, void* ctx) {
     int nt = 1;
 #ifdef _OPENMP
     nt = omp_get_max_threads();
 #endif
-    (void)nthreads_hint;
     int64_t cap = g->max_deg > 0 ? g->max_deg : 1;
     int32_t* hv = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap * (size_t)nt);
     int32_t* he = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap * (size_t)nt);
     if (!hv || !he) { free(hv); free(he); return ORC_E_NOMEM; }
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t u = 0; u < g->n; u++) {
+    for (int64_t iu = 0; iu < nlist; iu++) {
+        const int64_t u = list ? list[iu] : iu;
         int tid = 0;
 #ifdef _OPENMP
         tid = omp_get_thread_num();
@@ -411,6 +421,24 @@ int orc_count_multi(const orc_graph* g, const double* t, int nt, int64_t* counts
 
 int orc_count(const orc_graph* g, double t, int64_t out[2]) {
     return orc_count_multi(g, &t, 1, out);
+}
+
+/* Counts of the triangles whose lowest-ranked vertex is listed (a vertex sample of the
+ * node iterator; summed over all vertices it is orc_count). */
+int orc_count_vertices(const orc_graph* g, double t, const int64_t* us, int64_t k,
+                       int64_t out[2]) {
+    if (check_t(t)) return ORC_E_INVALID;
+    for (int64_t i = 0; i < k; i++)
+        if (us[i] < 0 || us[i] >= g->n) return ORC_E_INVALID;
+    double c = orc_c(t);
+    int th = orc_threads();
+    count_ctx cx = {g, &c, 1, (int64_t*)calloc((size_t)th * 2, sizeof(int64_t))};
+    if (!cx.cnt) return ORC_E_NOMEM;
+    int rc = orc_node_iterate_list(g, us, k, count_visit, &cx);
+    out[0] = out[1] = 0;
+    for (int q = 0; q < th; q++) { out[0] += cx.cnt[2 * q]; out[1] += cx.cnt[2 * q + 1]; }
+    free(cx.cnt);
+    return rc;
 }
 
 /* ---------------------------------------------------------------- enumeration */

@@ -158,10 +158,18 @@ int count_impl(utri_graph* g, double t, int method, int64_t out[2], hipStream_t 
     UTRI_TRY(utri_fill_u64(acc, 0, 2, s));
     WalkParams wp = base_params(method, c);
     wp.acc = (unsigned long long*)acc;
+    if (g->timing) UTRI_HIP_TRY(hipEventRecord(g->tev0, s));
     UTRI_TRY(utri_walk_launch(g, WALK_COUNT, wp, items, nitems, len, 0, s));
+    if (g->timing) UTRI_HIP_TRY(hipEventRecord(g->tev1, s));
     uint64_t h[2] = {0, 0};
     UTRI_HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
     UTRI_HIP_TRY(hipStreamSynchronize(s));
+    if (g->timing) {
+        float ms = 0.f;
+        UTRI_HIP_TRY(hipEventElapsedTime(&ms, g->tev0, g->tev1));
+        g->timing_ms += ms;
+        g->timing_launches += 1;
+    }
     out[0] = (int64_t)h[0];
     out[1] = (int64_t)h[1];
     return UTRI_OK;
@@ -560,6 +568,56 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
     UTRI_HIP_TRY(hipStreamWaitEvent(s, B.ev, 0));
     // thresholds / seed were uploaded from host memory owned by this call
     UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
+int utri_walk_stats(utri_graph* g, double t, int method, int64_t out[5], void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!out || !t_ok(t)) return UTRI_E_INVALID;
+    if (method < UTRI_PLAIN || method > UTRI_PRUNED_L3) return UTRI_E_INVALID;
+    hipStream_t s = as_stream(hip_stream);
+    const double c = utri_c_of_t(t);
+    int64_t *items, *nitems;
+    int32_t* len;
+    UTRI_TRY(walk_prepare_for(g, method, c, s, &items, &nitems, &len));
+    void *acc, *tmp, *tot;
+    UTRI_TRY(utri_scratch(g, SCR_ACC, sizeof(uint64_t) * 4, &acc));
+    UTRI_TRY(utri_scratch(g, SCR_IOFF, sizeof(int64_t) * (size_t)(g->n + 1), &tmp));
+    UTRI_TRY(utri_scratch(g, SCR_OUT, sizeof(int64_t) * 4, &tot));
+    UTRI_TRY(utri_fill_u64(acc, 0, 3, s));
+    UTRI_TRY(utri_fill_u64(tot, 0, 1, s));
+    // m_c = sum of the kept source-row prefixes (the k_items pass has consumed SCR_IOFF)
+    UTRI_TRY(utri_scan_i32(g, len, (int64_t*)tmp, g->n, (int64_t*)tot, s));
+    WalkParams wp = base_params(method, c);
+    wp.acc = (unsigned long long*)acc;
+    UTRI_TRY(utri_walk_launch(g, WALK_STATS, wp, items, nitems, len, 0, s));
+    uint64_t h[3] = {0, 0, 0};
+    int64_t mc = 0, ni = 0;
+    UTRI_HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipMemcpyAsync(&mc, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipMemcpyAsync(&ni, nitems, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    out[0] = mc;
+    out[1] = (int64_t)h[1];
+    out[2] = (int64_t)h[0];
+    out[3] = (int64_t)h[2];
+    out[4] = ni;
+    return UTRI_OK;
+}
+
+int utri_timing(utri_graph* g, int enable, double* ms, int64_t* launches) {
+    UTRI_TRY(check_graph(g));
+    if (enable == 1) {
+        if (!g->tev0) UTRI_HIP_TRY(hipEventCreate(&g->tev0));
+        if (!g->tev1) UTRI_HIP_TRY(hipEventCreate(&g->tev1));
+        g->timing = 1;
+        g->timing_ms = 0.0;
+        g->timing_launches = 0;
+    } else if (enable == 0) {
+        g->timing = 0;
+    }
+    if (ms) *ms = g->timing_ms;
+    if (launches) *launches = g->timing_launches;
     return UTRI_OK;
 }
 

@@ -415,6 +415,8 @@ static void free_graph(utri_graph* g) {
     if (g->batch.graph) (void)hipGraphDestroy(g->batch.graph);
     if (g->batch.stream) (void)hipStreamDestroy(g->batch.stream);
     if (g->batch.ev) (void)hipEventDestroy(g->batch.ev);
+    if (g->tev0) (void)hipEventDestroy(g->tev0);
+    if (g->tev1) (void)hipEventDestroy(g->tev1);
     delete g;
 }
 

@@ -123,6 +123,12 @@ struct utri_graph {
     int walk_blocks_per_cu = 8;
     int sample_chunk = 2048;
 
+    // event timing of the counting walk kernel (utri_timing)
+    int timing = 0;
+    double timing_ms = 0.0;
+    int64_t timing_launches = 0;
+    hipEvent_t tev0 = nullptr, tev1 = nullptr;
+
     UtriBatchGraph batch;
 };
 
@@ -274,7 +280,14 @@ __device__ inline int utri_bin_of(double s, const double* cv, int nt, bool& bal)
 int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int64_t** items,
                       int64_t** n_items_dev, int32_t** len);
 
-enum WalkMode { WALK_COUNT = 0, WALK_HIST = 1, WALK_EXPECTED = 2, WALK_ENUM_COUNT = 3, WALK_ENUM_FILL = 4 };
+enum WalkMode {
+    WALK_COUNT = 0,
+    WALK_HIST = 1,
+    WALK_EXPECTED = 2,
+    WALK_ENUM_COUNT = 3,
+    WALK_ENUM_FILL = 4,
+    WALK_STATS = 5,  // acc[0] = hash hits, acc[1] = target elements (first chunk), acc[2] = all streamed
+};
 
 struct WalkParams {
     double c = 0.0;          // decision threshold (COUNT / ENUM)

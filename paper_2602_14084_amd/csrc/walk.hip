@@ -58,6 +58,7 @@ struct WalkLaneState {
     uint64_t tri = 0;              // EXPECTED
     uint64_t slo = 0;              // EXPECTED: sum of low 32 bits of each fixed-point term
     int64_t shi = 0;               // EXPECTED: sum of the terms shifted right by 32
+    uint64_t wt = 0, wt_all = 0;   // STATS: streamed target elements (first chunk / all)
 };
 
 // Process one work item. `it` is the item's index in the items array.
@@ -119,6 +120,10 @@ __device__ void walk_item(const WalkParams& wp, const int64_t* __restrict__ o_of
                 }
                 lv = a;
             }
+            if (MODE == WALK_STATS) {
+                st.wt_all += (uint64_t)lv;
+                if (chunk == 0) st.wt += (uint64_t)lv;
+            }
         }
         const int incl = (int)utri_wave_incl_scan((int64_t)lv);
         const int total = __shfl(incl, UTRI_WAVE - 1, UTRI_WAVE);
@@ -155,6 +160,8 @@ __device__ void walk_item(const WalkParams& wp, const int64_t* __restrict__ o_of
                         bool bal;
                         const int bin = utri_bin_of(s, wp.cvals, wp.nt, bal);
                         if (bin > 0) atomicAdd(&L.hist[bal ? 0 : 1][bin], 1ull);
+                    } else if (MODE == WALK_STATS) {
+                        st.tri++;
                     } else if (MODE == WALK_EXPECTED) {
                         const int64_t t = utri_fix62(s);
                         st.tri++;
@@ -224,6 +231,14 @@ __device__ void walk_flush(const WalkParams& wp, WaveLds& L, WalkLaneState& st) 
         if (lane == 0) {
             if (tri) atomicAdd(&wp.acc[0], (unsigned long long)tri);
             utri_atomic_add_u128(&wp.acc[1], lo, hi);
+        }
+    } else if (MODE == WALK_STATS) {
+        const uint64_t a = utri_wave_sum_u64(st.tri), b = utri_wave_sum_u64(st.wt),
+                       c = utri_wave_sum_u64(st.wt_all);
+        if (lane == 0) {
+            atomicAdd(&wp.acc[0], (unsigned long long)a);
+            atomicAdd(&wp.acc[1], (unsigned long long)b);
+            atomicAdd(&wp.acc[2], (unsigned long long)c);
         }
     } else if (MODE == WALK_HIST) {
         utri_wave_sync();
@@ -355,6 +370,10 @@ int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_
             break;
         case WALK_ENUM_FILL:
             hipLaunchKernelGGL(k_walk<WALK_ENUM_FILL>, dim3(blocks), dim3(TPB), 0, s, wp,
+                               g->o_off, g->o_adj, g->o_d, len, g->perm, items, n_items_dev);
+            break;
+        case WALK_STATS:
+            hipLaunchKernelGGL(k_walk<WALK_STATS>, dim3(blocks), dim3(TPB), 0, s, wp,
                                g->o_off, g->o_adj, g->o_d, len, g->perm, items, n_items_dev);
             break;
         default:

@@ -35,7 +35,7 @@ ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
     "utri_expected_grad", "utri_edge_local", "utri_sample", "utri_batch", "utri_autotune",
-    "utri_strerror",
+    "utri_walk_stats", "utri_timing", "utri_strerror",
 ]
 
 _lib = None
@@ -72,6 +72,8 @@ def lib():
     L.utri_sample.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, C.c_int, vp, vp]
     L.utri_batch.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, vp, vp, C.c_int, vp]
     L.utri_autotune.argtypes = [vp, f64, C.c_char_p, vp]
+    L.utri_walk_stats.argtypes = [vp, f64, C.c_int, P(i64), vp]
+    L.utri_timing.argtypes = [vp, C.c_int, P(f64), P(i64)]
     L.utri_strerror.argtypes = [C.c_int]
     L.utri_strerror.restype = C.c_char_p
     for name in ABI_FUNCTIONS:
@@ -254,6 +256,22 @@ def utri_batch(h, ts, k, worlds, seed, use_graph=True, exact=None, est=None, wan
 def utri_autotune(h, t, cache_path=None, stream=None):
     cp = cache_path.encode() if cache_path else None
     _check(lib().utri_autotune(h, float(t), cp, _stream(stream)), "utri_autotune")
+
+
+def utri_walk_stats(h, t, method=UTRI_PRUNED, stream=None):
+    """dict(m_c, target_elems, candidates, streamed, items) of one counting walk at t."""
+    out = (C.c_int64 * 5)()
+    _check(lib().utri_walk_stats(h, float(t), method, out, _stream(stream)), "utri_walk_stats")
+    keys = ["m_c", "target_elems", "candidates", "streamed", "items"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def utri_timing(h, enable):
+    """(ms, launches) of the timed counting-walk kernels; enable 1 resets, 0 stops, 2 reads."""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(lib().utri_timing(h, int(enable), C.byref(ms), C.byref(n)), "utri_timing")
+    return ms.value, n.value
 
 
 def utri_strerror(code):
