@@ -45,6 +45,7 @@ def _load():
     lib.orc_expected.argtypes = [vp, _f64p, _i64p, _u64p, _i64p]
     lib.orc_grad.argtypes = [vp, _i64p, C.c_int64, _f64p]
     lib.orc_edge_local.argtypes = [vp, _f64p, C.c_int, _i64p, C.c_int64, _i64p]
+    lib.orc_local_expected.argtypes = [vp, _i64p, _f64p, C.c_int64, _i64p, _u64p]
     lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     lib.orc_sample_edge.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64]
     lib.orc_sample_edge.restype = C.c_int64
@@ -157,6 +158,32 @@ class OracleGraph:
         if rc != OK:
             raise OracleError(rc, "grad")
         return out
+
+    def local_expected_fixed(self, eids, q):
+        """Exact N_e(q) (Python ints) with L_e(q) = N * 2^-63 = sum over triangles through e
+        of P_bal with P+(e) replaced by q."""
+        eids = np.ascontiguousarray(eids, np.int64)
+        q = np.ascontiguousarray(np.broadcast_to(np.asarray(q, np.float64), eids.shape))
+        hi = np.zeros(eids.shape[0], np.int64)
+        lo = np.zeros(eids.shape[0], np.uint64)
+        rc = self._lib.orc_local_expected(self._h, _p(eids, _i64p), _p(q, _f64p),
+                                          int(eids.shape[0]), _p(hi, _i64p), _p(lo, _u64p))
+        if rc != OK:
+            raise OracleError(rc, "local_expected")
+        return [(int(h) << 64) + int(l) for h, l in zip(hi, lo)]
+
+    def local_central_difference(self, eids, h):
+        """(L_e(fl(p+h)) - L_e(fl(p-h))) / (fl(p+h) - fl(p-h)) per edge, exact up to the
+        2^-63 rounding of each term (E is affine in p_e, so this equals dE/dp_e)."""
+        _, _, p = self.edges()
+        eids = np.ascontiguousarray(eids, np.int64)
+        qp = np.minimum(p[eids] + h, 1.0)
+        qm = np.maximum(p[eids] - h, 0.0)
+        Np = self.local_expected_fixed(eids, qp)
+        Nm = self.local_expected_fixed(eids, qm)
+        from fractions import Fraction
+        return np.array([float(Fraction(a - b, 2 ** 63) / (Fraction(float(x)) - Fraction(float(y))))
+                         for a, b, x, y in zip(Np, Nm, qp, qm)])
 
     def edge_local(self, ts, eids=None):
         ts = np.atleast_1d(np.ascontiguousarray(ts, dtype=np.float64))

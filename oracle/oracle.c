@@ -592,6 +592,36 @@ int orc_grad(const orc_graph* g, const int64_t* eids, int64_t k, double* out) {
     return ORC_OK;
 }
 
+/* Local expected balanced count of edge e with its P+ replaced by q:
+ * L_e(q) = sum over triangles (e, f, g) of P_bal = (1 - s)/2, s = d(q) d_f d_g.
+ * Returned exactly as N = cnt * 2^62 - sum fix62(s) (two's complement hi:lo), so
+ * L_e(q) = N * 2^-63 and a central difference of L_e is exact up to 2^-63 per term. */
+int orc_local_expected(const orc_graph* g, const int64_t* eids, const double* q, int64_t k,
+                       int64_t* n_hi, uint64_t* n_lo) {
+    if (check_eids(g, eids, k)) return ORC_E_INVALID;
+    for (int64_t i = 0; i < k; i++)
+        if (!(q[i] >= 0.0 && q[i] <= 1.0)) return ORC_E_INVALID;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < k; i++) {
+        int64_t e = eids[i];
+        int32_t a = g->lo[e], b = g->hi[e];
+        double de = orc_d(q[i]);
+        __int128 S = 0, cnt = 0;
+        for (int64_t j = g->off[a]; j < g->off[a + 1]; j++) {
+            int32_t w = g->nbr[j];
+            if (w == b) continue;
+            int32_t ebw = orc_find(g, b, w);
+            if (ebw < 0) continue;
+            S += (__int128)orc_fix62(orc_s(de, g->d[g->eid[j]], g->d[ebw]));
+            cnt += 1;
+        }
+        __int128 N = (cnt << 62) - S;
+        n_hi[i] = (int64_t)(N >> 64);
+        n_lo[i] = (uint64_t)N;
+    }
+    return ORC_OK;
+}
+
 /* local counts at each threshold: out[i][j][0/1] = (balanced, unbalanced) triangles
  * through edge eids[i] at t_j */
 static void edge_local_one(const orc_graph* g, int64_t e, const double* c, int nt, int64_t* out) {

@@ -35,9 +35,9 @@ __global__ void k_symlen(const int64_t* __restrict__ off, const double* __restri
 
 __global__ void __launch_bounds__(TPB) k_sample(SampleParams sp, SampleGraph G,
                                                 const int32_t* __restrict__ slen, int64_t units) {
-    __shared__ WaveLds lds[WPB];
+    __shared__ SegLds lds[WPB];
     const int wib = threadIdx.x / UTRI_WAVE;
-    WaveLds& L = lds[wib];
+    SegLds& L = lds[wib];
     const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
     const int64_t W = (int64_t)gridDim.x * WPB;
     const int64_t upw = (sp.k + sp.chunk - 1) / sp.chunk;

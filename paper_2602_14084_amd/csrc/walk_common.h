@@ -1,4 +1,4 @@
-// walk_common.h -- per-wave LDS layout and the edge-sampling work unit shared by the
+// walk_common.h -- per-wave LDS layouts and the edge-sampling work unit shared by the
 // sampler kernels and the fused batch kernel.
 #pragma once
 
@@ -12,18 +12,25 @@ constexpr int CAP = 512;       // hash-side entries per walk item
 constexpr int HS = 2 * CAP;    // LDS table slots (load factor <= 1/2)
 constexpr int NB = 65;         // histogram bins (nt + 1 <= 65)
 
-struct WaveLds {
+// LDS of one wave of the walk: the staged source chunk as an open-addressing table
+struct WalkLds {
     int32_t key[HS];
     uint16_t pos[HS];
+};
+
+struct HistLds {
+    unsigned long long hist[2][NB];
+};
+
+// LDS of one wave of a flattened strip loop (sampler, backward)
+struct SegLds {
     int32_t end[UTRI_WAVE];       // inclusive prefix of segment lengths
     int64_t xoff[UTRI_WAVE];      // start of the streamed row of each segment
+    int64_t yoff[UTRI_WAVE];      // start of the probe-side row
+    int64_t hoff[UTRI_WAVE];      // start of the probe-side table
+    int32_t hlg[UTRI_WAVE];       // log2 size of the probe-side table
     double dseg[UTRI_WAVE];       // d of the segment's own edge
-    int32_t vseg[UTRI_WAVE];      // walk: v of the segment
-    int64_t yoff[UTRI_WAVE];      // sampler: start of the probe-side row
-    int64_t hoff[UTRI_WAVE];      // sampler: start of the probe-side table
-    int32_t hlg[UTRI_WAVE];       // sampler: log2 size of the probe-side table
-    unsigned long long hist[2][NB];   // walk histogram (per wave, whole launch)
-    unsigned long long shist[2][NB];  // sampler histogram (per work unit)
+    unsigned long long shist[2][NB];
 };
 
 __device__ inline int seg_search(const int32_t* end, int f) {
@@ -34,6 +41,17 @@ __device__ inline int seg_search(const int32_t* end, int f) {
         if (end[mid] > f) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+// wave-uniform broadcast of lane `src` (src must be wave-uniform)
+__device__ inline int bcast_i32(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+__device__ inline int64_t bcast_i64(int64_t x, int src) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)x, src);
+    const int hi = __builtin_amdgcn_readlane((int)((uint64_t)x >> 32), src);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+__device__ inline double bcast_f64(double x, int src) {
+    return __longlong_as_double(bcast_i64(__double_as_longlong(x), src));
 }
 
 struct SampleGraph {
@@ -75,10 +93,11 @@ __device__ inline int log2_size(int64_t size) {
 // which is added to hist[world][2][nt+1] at the end of the unit.
 __device__ inline void sample_unit(const SampleParams& sp, const SampleGraph& G,
                                    const int32_t* __restrict__ slen, int32_t world,
-                                   int64_t i_begin, int64_t i_end, WaveLds& L) {
+                                   int64_t i_begin, int64_t i_end, SegLds& L) {
     const int lane = utri_lane();
     for (int q = lane; q < 2 * NB; q += UTRI_WAVE) L.shist[q / NB][q % NB] = 0;
     utri_wave_sync();
+    const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
     for (int64_t i0 = i_begin; i0 < i_end; i0 += UTRI_WAVE) {
         const int64_t i = i0 + lane;
         int work = 0;
@@ -86,7 +105,6 @@ __device__ inline void sample_unit(const SampleParams& sp, const SampleGraph& G,
         int lg = 0;
         double de = 0.0;
         if (i < i_end) {
-            const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
             const int64_t e = utri_sample_edge(seed, (uint32_t)world, (uint64_t)i, G.m);
             de = G.e_d[e];
             if (fabs(de) >= sp.cmin) {

@@ -124,9 +124,20 @@ def test_enumerate_which_and_capacity():
     g = gpu_graph(n, lo, hi, p)
     bal, unb = g.enumerate(0.6, which=utri.UTRI_BAL)
     assert np.array_equal(bal.cpu().numpy(), ob) and unb.shape[0] == 0
-    with pytest.raises(utri.UtriError) as ei:
-        utri.utri_enumerate(g.handle, 0.6, cap=(ob.shape[0] - 1, ou.shape[0]))
-    assert ei.value.code == utri.UTRI_E_CAPACITY
+    # the raw C call reports the sizes with UTRI_E_CAPACITY when a buffer is too small
+    import ctypes as C
+    cb, cu = ob.shape[0] - 1, ou.shape[0]
+    bb = torch.empty((cb, 3), dtype=torch.int32, device="cuda")
+    ub = torch.empty((cu, 3), dtype=torch.int32, device="cuda")
+    counts = (C.c_int64 * 2)()
+    rc = utri.lib().utri_enumerate(g.handle, 0.6, utri.UTRI_PRUNED, utri.UTRI_BOTH,
+                                   C.c_void_p(bb.data_ptr()), cb, C.c_void_p(ub.data_ptr()), cu,
+                                   counts, 1, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == utri.UTRI_E_CAPACITY
+    assert (counts[0], counts[1]) == (ob.shape[0], ou.shape[0])
+    # the binding grows its buffers and retries
+    bal, unb = utri.utri_enumerate(g.handle, 0.6, cap=(cb, cu))
+    assert np.array_equal(bal.cpu().numpy(), ob) and np.array_equal(unb.cpu().numpy(), ou)
 
 
 def test_expected_matches_oracle_exactly():

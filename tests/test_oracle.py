@@ -144,6 +144,45 @@ def test_grad_central_difference():
         assert abs(fd - gr[e]) <= 1e-8 * max(1.0, abs(E0)), (e, fd, gr[e])
 
 
+def test_local_expected_matches_exact_rational():
+    """L_e(q) = sum over triangles through e of P_bal with P+(e) := q, exact rationals."""
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()[:4]):
+        for dist in ["dyadic16", "uniform"]:
+            p = inputs.draw_p(lo.shape[0], dist, 51 + gi)
+            g = load(n, lo, hi, p)
+            E = bf.edge_map(lo, hi, p)
+            eids = np.arange(lo.shape[0])
+            for q in [0.0, 0.3125, float(p[0]), 1.0]:
+                N = g.local_expected_fixed(eids, q)
+                for e in eids:
+                    key = (int(lo[e]), int(hi[e]))
+                    exact = F(0)
+                    cnt = 0
+                    for tri in bf.triangles(n, E):
+                        edges = [(tri[0], tri[1]), (tri[0], tri[2]), (tri[1], tri[2])]
+                        if key not in edges:
+                            continue
+                        cnt += 1
+                        exact += bf.p_bal(*[F(q) if x == key else E[x] for x in edges])
+                    got = F(N[e], 2 ** 63)
+                    if dist == "dyadic16" and q in (0.0, 0.3125, 1.0):
+                        assert got == exact
+                    else:
+                        assert abs(got - exact) <= F(cnt, 2 ** 62) + F(cnt, 2 ** 50)
+
+
+def test_local_central_difference_equals_gradient():
+    n, lo, hi = inputs.chung_lu_graph(400, 2.5, 5000.0, 14)
+    p = inputs.draw_p(lo.shape[0], "uniform_05_95", 15)
+    g = load(n, lo, hi, p)
+    eids = np.random.default_rng(2).integers(0, lo.shape[0], 200)
+    fd = g.local_central_difference(eids, 1e-6)
+    gr = g.grad(eids)
+    _, _, _ = g.expected()
+    scale = np.maximum(np.abs(gr), 1.0)
+    assert np.all(np.abs(fd - gr) <= 1e-9 * scale), np.max(np.abs(fd - gr) / scale)
+
+
 # ---------------------------------------------------------------- closed forms
 
 def dense_adj(n, lo, hi, vals=None):
