@@ -373,7 +373,7 @@ int utri_enumerate(utri_graph* g, double t, int method, int which, int32_t* bal,
     int64_t *items, *nitems;
     int32_t* len;
     UTRI_TRY(walk_prepare_for(g, method, c, s, &items, &nitems, &len));
-    const int64_t bound = (int64_t)utri_walk_items_bound(g) + 1;
+    const int64_t bound = utri_walk_items_bound(g) + 1;
     void *pc, *po, *ptot;
     UTRI_TRY(utri_scratch(g, SCR_ICNT2, sizeof(int64_t) * 2 * bound, &pc));
     UTRI_TRY(utri_scratch(g, SCR_IOFF2, sizeof(int64_t) * 2 * bound, &po));

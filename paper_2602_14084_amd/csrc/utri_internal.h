@@ -303,6 +303,7 @@ struct WalkParams {
     int32_t* out_bal = nullptr;
     int32_t* out_unbal = nullptr;
     int which = UTRI_BOTH;
+    int64_t lb = 0;                     // first enumeration slot of the heavy items (set at launch)
 };
 
 int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_t* items,
@@ -331,7 +332,7 @@ int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const
                          hipStream_t s);
 int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
                            const int64_t* eids, int64_t k, int64_t* out, hipStream_t s);
-int utri_walk_items_bound(utri_graph* g);
+int64_t utri_walk_items_bound(utri_graph* g);
 int utri_grad_launch(utri_graph* g, double* grad, hipStream_t s);
 
 // generic helpers

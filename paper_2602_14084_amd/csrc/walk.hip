@@ -7,14 +7,16 @@
 // reduces each row to a prefix of length len[x]; the optional Lemma-3 cut shortens the
 // target row N+(v) further, per pair, to entries with |d_vw| * |d_uv| * max|d_u.| >= c.
 //
-// GPU mapping (one wave64 per work item, persistent grid):
-//   item = (u, chunk): the chunk's slice of N+(u) (at most CAP entries) is staged in an
-//   LDS open-addressing table (neighbour -> position). The wave then walks the target
-//   rows N+(v), v in N+(u), one row at a time: v, its row start and length are
-//   broadcast into scalar registers and the row is streamed coalesced, 64 entries per
-//   step, each lane probing one w in the table. Only hits read d values. The classify,
-//   count, histogram, fixed-point, enumeration and statistics epilogues are selected at
-//   compile time.
+// GPU mapping (persistent grid, two phases per work-group):
+//   * long source rows (len > CAP): one work-group per item (u, 2048-entry chunk). The
+//     chunk of N+(u) is staged in a work-group LDS open-addressing table and the four
+//     waves split the target rows N+(v) round-robin;
+//   * other source rows: one wave per item, the row staged in the wave's own table.
+//   A target row N+(v) is streamed coalesced with v, its start and length broadcast in
+//   scalar registers; each lane loads up to four ids ahead (64 apart) before probing
+//   them, so every wave keeps several loads in flight. Only hits read d values. The
+//   classify, count, histogram, fixed-point, enumeration and statistics epilogues are
+//   selected at compile time.
 #include <algorithm>
 
 #include "walk_common.h"
@@ -23,11 +25,30 @@ using namespace utri_dev;
 
 namespace {
 
+constexpr int CAPH = 2048;         // source entries per work-group item
+constexpr int HSH = 2 * CAPH;      // work-group table slots
+
 inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
 
+struct BlockLds {
+    int32_t key[HSH];
+    uint16_t pos[HSH];
+};
+
+union WalkShared {
+    WalkLds wave[WPB];
+    BlockLds block;
+};
+static_assert(sizeof(BlockLds) <= sizeof(WalkLds) * WPB, "work-group table must fit the wave tables");
+
+// Bounds of the two item lists: light items (one per source row with 2 <= len <= CAP)
+// and heavy items (len > CAP, ceil(len / CAPH) chunks per row).
+inline int64_t light_bound(const utri_graph* g) { return std::min<int64_t>(g->n, g->m / 2) + 1; }
+inline int64_t heavy_bound(const utri_graph* g) { return 2 * (g->m / CAP) + 2; }
+
 __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restrict__ dd,
-                         int64_t n, double c, int cap, int32_t* __restrict__ len,
-                         int32_t* __restrict__ icnt) {
+                         int64_t n, double c, int32_t* __restrict__ len,
+                         int32_t* __restrict__ lcnt, int32_t* __restrict__ hcnt) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int64_t a = off[v], b = off[v + 1];
@@ -40,17 +61,20 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
     } else {
         lo = b;
     }
-    int32_t L = (int32_t)(lo - a);
+    const int32_t L = (int32_t)(lo - a);
     len[v] = L;
-    if (icnt) icnt[v] = (L >= 2) ? (L + cap - 1) / cap : 0;
+    lcnt[v] = (L >= 2 && L <= CAP) ? 1 : 0;
+    hcnt[v] = (L > CAP) ? (L + CAPH - 1) / CAPH : 0;
 }
 
-__global__ void k_items(const int32_t* __restrict__ icnt, const int64_t* __restrict__ ioff,
-                        int64_t n, int64_t* __restrict__ items) {
+__global__ void k_items(const int32_t* __restrict__ lcnt, const int32_t* __restrict__ hcnt,
+                        const int64_t* __restrict__ loff, const int64_t* __restrict__ hoff,
+                        int64_t n, int64_t hbase, int64_t* __restrict__ items) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    int c = icnt[v];
-    int64_t o = ioff[v];
+    if (lcnt[v]) items[loff[v]] = v;
+    const int c = hcnt[v];
+    const int64_t o = hbase + hoff[v];
     for (int k = 0; k < c; k++) items[o + k] = ((int64_t)k << 32) | (int64_t)v;
 }
 
@@ -62,154 +86,255 @@ struct WalkLaneState {
     uint64_t wt = 0, wt_all = 0;   // STATS: streamed target elements (first chunk / all)
 };
 
-// Process one work item. `it` is the item's index in the items array.
-template <int MODE>
-__device__ void walk_item(const WalkParams& wp, const int64_t* __restrict__ o_off,
-                          const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
-                          const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                          int64_t item, int64_t it, WalkLds& L, HistLds* H,
-                          WalkLaneState& st) {
+// The staged source chunk and the current pair (u, v).
+struct RowCtx {
+    const int32_t* key;
+    const uint16_t* pos;
+    int lg;
+    uint32_t mask;
+    int64_t src_base;   // o_off[u] + chunk start: position of hash hits in o_adj / o_d
+    int32_t pu;         // perm[u] (enumeration)
+    int chunk;
+};
+
+// Stream the kept target row [ovs, ovs + lvs) of v, probing every entry in the table.
+template <int MODE, int UNR>
+__device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* __restrict__ o_adj,
+                                           const double* __restrict__ o_d,
+                                           const int32_t* __restrict__ perm, const RowCtx& R,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           HistLds* H, WalkLaneState& st, int64_t& run_b,
+                                           int64_t& run_u) {
     const int lane = utri_lane();
+    for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
+        int32_t w[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; k++) {
+            const int j = j0 + k * UTRI_WAVE + lane;
+            w[k] = (j < lvs) ? o_adj[ovs + j] : -2;  // -2 matches no key and no empty slot
+        }
+#pragma unroll
+        for (int k = 0; k < UNR; k++) {
+            const int j = j0 + k * UTRI_WAVE + lane;
+            bool is_b = false, is_u = false;
+            int hit = -1;
+            if (w[k] >= 0) {
+                uint32_t h = utri_hash32(w[k], R.lg);
+                for (;;) {
+                    const int kk = R.key[h];
+                    if (kk == w[k]) { hit = R.pos[h]; break; }
+                    if (kk == -1) break;
+                    h = (h + 1) & R.mask;
+                }
+            }
+            if (hit >= 0) {
+                const double dvw = o_d[ovs + j];
+                const double duw = o_d[R.src_base + hit];
+                if (MODE == WALK_STATS) {
+                    st.tri++;
+                } else {
+                    const double s = utri_tri_s(duvs, duw, dvw);
+                    if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) {
+                        if (s <= -wp.c) st.nb++;
+                        else if (s > wp.c) st.nu++;
+                    } else if (MODE == WALK_HIST) {
+                        bool bal;
+                        const int bin = utri_bin_of(s, wp.cvals, wp.nt, bal);
+                        if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
+                    } else if (MODE == WALK_EXPECTED) {
+                        const int64_t t = utri_fix62(s);
+                        st.tri++;
+                        st.slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
+                        st.shi += (t >> 32);
+                    } else if (MODE == WALK_ENUM_FILL) {
+                        is_b = (s <= -wp.c) && (wp.which & UTRI_BAL);
+                        is_u = (s > wp.c) && (wp.which & UTRI_UNBAL);
+                    }
+                }
+            }
+            if (MODE == WALK_ENUM_FILL) {
+                const uint64_t mb = __ballot(is_b);
+                const uint64_t mu = __ballot(is_u);
+                if (is_b || is_u) {
+                    int32_t a = R.pu, b = pv, c = perm[w[k]], t;
+                    if (b < a) { t = a; a = b; b = t; }
+                    if (c < b) { t = b; b = c; c = t; }
+                    if (b < a) { t = a; a = b; b = t; }
+                    const uint64_t lt = __lanemask_lt();
+                    int32_t* dst;
+                    int64_t slot;
+                    if (is_b) { dst = wp.out_bal; slot = run_b + __popcll(mb & lt); }
+                    else      { dst = wp.out_unbal; slot = run_u + __popcll(mu & lt); }
+                    dst[3 * slot] = a;
+                    dst[3 * slot + 1] = b;
+                    dst[3 * slot + 2] = c;
+                }
+                run_b += __popcll(mb);
+                run_u += __popcll(mu);
+            }
+        }
+    }
+    if (MODE == WALK_STATS && lane == 0) {
+        st.wt_all += (uint64_t)lvs;
+        if (R.chunk == 0) st.wt += (uint64_t)lvs;
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* __restrict__ o_adj,
+                                           const double* __restrict__ o_d,
+                                           const int32_t* __restrict__ perm, const RowCtx& R,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           HistLds* H, WalkLaneState& st, int64_t& run_b,
+                                           int64_t& run_u) {
+    if (lvs > 2 * UTRI_WAVE)
+        stream_row<MODE, 4>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+    else if (lvs > UTRI_WAVE)
+        stream_row<MODE, 2>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+    else
+        stream_row<MODE, 1>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+}
+
+// Load, on lane i, v = N+(u)[i0 + i] with its row start, kept length and d_uv.
+__device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t* __restrict__ o_off,
+                                             const int32_t* __restrict__ o_adj,
+                                             const double* __restrict__ o_d,
+                                             const int32_t* __restrict__ len, int64_t ou, int Lu,
+                                             int i0, double dmax_chunk, int& v, int64_t& ov,
+                                             int& lv, double& duv) {
+    const int i = i0 + utri_lane();
+    lv = 0; v = 0; ov = 0; duv = 0.0;
+    if (i < Lu) {
+        v = o_adj[ou + i];
+        duv = o_d[ou + i];
+        ov = o_off[v];
+        lv = len[v];
+        if (wp.lemma3 && lv > 0) {
+            // Lemma 3: keep w only if |d_vw| * (|d_uv| * max|d_uw|) >= c (with slack)
+            const double P = __dmul_rn(fabs(duv), dmax_chunk);
+            int a = 0, b = lv;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (__dmul_rn(fabs(o_d[ov + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
+            }
+            lv = a;
+        }
+    }
+}
+
+// Stage `cl` source entries starting at o_adj[base] into an open-addressing table of
+// 2^lg slots; `tid` / `nthreads` are the caller's lanes (one wave or one work-group).
+__device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, int64_t base, int cl,
+                                            int32_t* key, uint16_t* pos, int lg, int tid,
+                                            int nthreads) {
+    const uint32_t mask = (1u << lg) - 1u;
+    for (int j = tid; j < cl; j += nthreads) {
+        const int32_t w = o_adj[base + j];
+        uint32_t h = utri_hash32(w, lg);
+        for (;;) {
+            const int old = atomicCAS(&key[h], -1, w);
+            if (old == -1) { pos[h] = (uint16_t)j; break; }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+__device__ __forceinline__ int table_lg(int cl) {
+    int lg = 1;
+    while ((1 << lg) < 2 * cl) lg++;
+    return lg;
+}
+
+// Wave item: source row u with 2 <= len <= CAP, staged in the wave's own table.
+template <int MODE>
+__device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
+                               const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
+                               const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
+                               int u, int64_t it, WalkLds& L, HistLds* H, WalkLaneState& st) {
+    const int lane = utri_lane();
+    const int64_t ou = o_off[u];
+    const int Lu = len[u];
+    const int lg = table_lg(Lu);
+    const int size = 1 << lg;
+    for (int i = lane; i < size; i += UTRI_WAVE) L.key[i] = -1;
+    utri_wave_sync();
+    stage_table(o_adj, ou, Lu, L.key, L.pos, lg, lane, UTRI_WAVE);
+    utri_wave_sync();
+    RowCtx R{L.key, L.pos, lg, (uint32_t)(size - 1), ou,
+             (MODE == WALK_ENUM_FILL) ? perm[u] : 0, 0};
+    const double dmax_chunk = fabs(o_d[ou]);
+    int64_t run_b = 0, run_u = 0;
+    if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[it]; run_u = wp.off_u[it]; }
+    for (int i0 = 0; i0 < Lu; i0 += UTRI_WAVE) {
+        int v, lv;
+        int64_t ov;
+        double duv;
+        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv);
+        const int nv = min(UTRI_WAVE, Lu - i0);
+        for (int si = 0; si < nv; si++) {
+            const int lvs = bcast_i32(lv, si);
+            if (lvs == 0) continue;
+            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)] : 0;
+            stream_any<MODE>(wp, o_adj, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
+                             pv, H, st, run_b, run_u);
+        }
+    }
+    if (MODE == WALK_ENUM_COUNT) {
+        const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
+        if (lane == 0) { wp.cnt_b[it] = (int64_t)nb; wp.cnt_u[it] = (int64_t)nu; }
+        st.nb = st.nu = 0;
+    }
+    utri_wave_sync();
+}
+
+// Work-group item: chunk `chunk` (CAPH entries) of a long source row, one shared table,
+// target rows split round-robin over the four waves. Enumeration slots are per wave.
+template <int MODE>
+__device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict__ o_off,
+                                const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
+                                const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
+                                int64_t item, int64_t hq, BlockLds& B, HistLds* H,
+                                WalkLaneState& st) {
+    const int lane = utri_lane();
+    const int wib = threadIdx.x / UTRI_WAVE;
     const int u = (int)(item & 0xFFFFFFFF);
     const int chunk = (int)(item >> 32);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
-    const int cb = chunk * CAP;
-    const int cl = min(CAP, Lu - cb);
-    int lg = 1;
-    while ((1 << lg) < 2 * cl) lg++;
+    const int cb = chunk * CAPH;
+    const int cl = min(CAPH, Lu - cb);
+    const int lg = table_lg(cl);
     const int size = 1 << lg;
-    const uint32_t mask = (uint32_t)(size - 1);
-
-    // stage the chunk of N+(u) as (neighbour -> position) in the wave's LDS table
-    for (int i = lane; i < size; i += UTRI_WAVE) L.key[i] = -1;
-    utri_wave_sync();
-    for (int j = lane; j < cl; j += UTRI_WAVE) {
-        const int32_t w = o_adj[ou + cb + j];
-        uint32_t h = utri_hash32(w, lg);
-        for (;;) {
-            const int old = atomicCAS(&L.key[h], -1, w);
-            if (old == -1) { L.pos[h] = (uint16_t)j; break; }
-            h = (h + 1) & mask;
-        }
-    }
-    utri_wave_sync();
-
+    __syncthreads();  // the previous item's probes are done
+    for (int i = threadIdx.x; i < size; i += TPB) B.key[i] = -1;
+    __syncthreads();
+    stage_table(o_adj, ou + cb, cl, B.key, B.pos, lg, threadIdx.x, TPB);
+    __syncthreads();
+    RowCtx R{B.key, B.pos, lg, (uint32_t)(size - 1), ou + cb,
+             (MODE == WALK_ENUM_FILL) ? perm[u] : 0, chunk};
     const double dmax_chunk = fabs(o_d[ou + cb]);
-    const int32_t pu = (MODE == WALK_ENUM_FILL) ? perm[u] : 0;
+    const int64_t slot = wp.lb + 4 * hq + wib;
     int64_t run_b = 0, run_u = 0;
-    if (MODE == WALK_ENUM_FILL) {
-        run_b = wp.off_b[it];
-        run_u = wp.off_u[it];
-    }
-
+    if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[slot]; run_u = wp.off_u[slot]; }
     for (int i0 = 0; i0 < Lu; i0 += UTRI_WAVE) {
-        // lane i holds v = N+(u)[i0 + i], its row start, kept length and d_uv
-        const int i = i0 + lane;
-        int lv = 0, v = 0;
-        int64_t ov = 0;
-        double duv = 0.0;
-        if (i < Lu) {
-            v = o_adj[ou + i];
-            duv = o_d[ou + i];
-            ov = o_off[v];
-            lv = len[v];
-            if (wp.lemma3 && lv > 0) {
-                // Lemma 3: keep w only if |d_vw| * (|d_uv| * max|d_uw|) >= c (with slack)
-                const double P = __dmul_rn(fabs(duv), dmax_chunk);
-                int a = 0, b = lv;
-                while (a < b) {
-                    const int mid = (a + b) >> 1;
-                    if (__dmul_rn(fabs(o_d[ov + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
-                }
-                lv = a;
-            }
-            if (MODE == WALK_STATS) {
-                st.wt_all += (uint64_t)lv;
-                if (chunk == 0) st.wt += (uint64_t)lv;
-            }
-        }
+        int v, lv;
+        int64_t ov;
+        double duv;
+        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv);
         const int nv = min(UTRI_WAVE, Lu - i0);
-        for (int s_i = 0; s_i < nv; s_i++) {
-            const int lvs = bcast_i32(lv, s_i);
+        for (int si = wib; si < nv; si += WPB) {
+            const int lvs = bcast_i32(lv, si);
             if (lvs == 0) continue;
-            const int64_t ovs = bcast_i64(ov, s_i);
-            const double duvs = bcast_f64(duv, s_i);
-            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, s_i)] : 0;
-            for (int j0 = 0; j0 < lvs; j0 += UTRI_WAVE) {
-                const int j = j0 + lane;
-                bool is_b = false, is_u = false;
-                int32_t tw = 0;
-                if (j < lvs) {
-                    const int32_t w = o_adj[ovs + j];
-                    uint32_t h = utri_hash32(w, lg);
-                    int hit = -1;
-                    for (;;) {
-                        const int k = L.key[h];
-                        if (k == w) { hit = L.pos[h]; break; }
-                        if (k == -1) break;
-                        h = (h + 1) & mask;
-                    }
-                    if (hit >= 0) {
-                        const double dvw = o_d[ovs + j];
-                        const double duw = o_d[ou + cb + hit];
-                        if (MODE == WALK_STATS) {
-                            st.tri++;
-                        } else {
-                            const double s = utri_tri_s(duvs, duw, dvw);
-                            if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) {
-                                if (s <= -wp.c) st.nb++;
-                                else if (s > wp.c) st.nu++;
-                            } else if (MODE == WALK_HIST) {
-                                bool bal;
-                                const int bin = utri_bin_of(s, wp.cvals, wp.nt, bal);
-                                if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
-                            } else if (MODE == WALK_EXPECTED) {
-                                const int64_t t = utri_fix62(s);
-                                st.tri++;
-                                st.slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
-                                st.shi += (t >> 32);
-                            } else if (MODE == WALK_ENUM_FILL) {
-                                is_b = (s <= -wp.c) && (wp.which & UTRI_BAL);
-                                is_u = (s > wp.c) && (wp.which & UTRI_UNBAL);
-                                tw = w;
-                            }
-                        }
-                    }
-                }
-                if (MODE == WALK_ENUM_FILL) {
-                    const uint64_t mb = __ballot(is_b);
-                    const uint64_t mu = __ballot(is_u);
-                    if (is_b || is_u) {
-                        int32_t a = pu, b = pv, c = perm[tw], t;
-                        if (b < a) { t = a; a = b; b = t; }
-                        if (c < b) { t = b; b = c; c = t; }
-                        if (b < a) { t = a; a = b; b = t; }
-                        const uint64_t lt = __lanemask_lt();
-                        int32_t* dst;
-                        int64_t slot;
-                        if (is_b) { dst = wp.out_bal; slot = run_b + __popcll(mb & lt); }
-                        else      { dst = wp.out_unbal; slot = run_u + __popcll(mu & lt); }
-                        dst[3 * slot] = a;
-                        dst[3 * slot + 1] = b;
-                        dst[3 * slot + 2] = c;
-                    }
-                    run_b += __popcll(mb);
-                    run_u += __popcll(mu);
-                }
-            }
+            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)] : 0;
+            stream_any<MODE>(wp, o_adj, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
+                             pv, H, st, run_b, run_u);
         }
     }
     if (MODE == WALK_ENUM_COUNT) {
-        const uint64_t item_nb = utri_wave_sum_u64(st.nb);
-        const uint64_t item_nu = utri_wave_sum_u64(st.nu);
-        if (lane == 0) {
-            wp.cnt_b[it] = (int64_t)item_nb;
-            wp.cnt_u[it] = (int64_t)item_nu;
-        }
+        const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
+        if (lane == 0) { wp.cnt_b[slot] = (int64_t)nb; wp.cnt_u[slot] = (int64_t)nu; }
         st.nb = st.nu = 0;
     }
-    utri_wave_sync();
 }
 
 template <int MODE>
@@ -252,6 +377,30 @@ __device__ void walk_flush(const WalkParams& wp, HistLds* H, WalkLaneState& st) 
     }
 }
 
+// Both phases of the walk for one work-group: heavy items cooperatively, then light
+// items one per wave. Heaviest rows (highest ids) go first in both lists.
+template <int MODE>
+__device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_off,
+                            const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
+                            const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
+                            const int64_t* __restrict__ items, int64_t nl, int64_t nh,
+                            WalkShared& S, HistLds* H, WalkLaneState& st) {
+    const int wib = threadIdx.x / UTRI_WAVE;
+    for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
+        const int64_t hq = nh - 1 - q;
+        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, S.block,
+                              H, st);
+    }
+    __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
+    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
+    const int64_t W = (int64_t)gridDim.x * WPB;
+    for (int64_t q = gw; q < nl; q += W) {
+        const int64_t it = nl - 1 - q;
+        walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, (int)items[it], it, S.wave[wib], H,
+                             st);
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __restrict__ o_off,
                                               const int32_t* __restrict__ o_adj,
@@ -260,27 +409,21 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
                                               const int32_t* __restrict__ perm,
                                               const int64_t* __restrict__ items,
                                               const int64_t* __restrict__ n_items_dev) {
-    __shared__ WalkLds lds[WPB];
+    __shared__ WalkShared S;
     __shared__ HistLds hlds[MODE == WALK_HIST ? WPB : 1];
     const int wib = threadIdx.x / UTRI_WAVE;
-    WalkLds& L = lds[wib];
     HistLds* H = &hlds[MODE == WALK_HIST ? wib : 0];
     if (MODE == WALK_HIST) {
         for (int q = utri_lane(); q < 2 * NB; q += UTRI_WAVE) H->hist[q / NB][q % NB] = 0;
         utri_wave_sync();
     }
-    const int64_t nitems = *n_items_dev;
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
-    const int64_t W = (int64_t)gridDim.x * WPB;
     WalkLaneState st;
-    for (int64_t q = gw; q < nitems; q += W) {
-        const int64_t it = nitems - 1 - q;  // heaviest vertices (highest ids) first
-        walk_item<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, L, H, st);
-    }
+    walk_phases<MODE>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0], n_items_dev[1], S,
+                      H, st);
     walk_flush<MODE>(wp, H, st);
 }
 
-// Fused batch: walk items (threshold histogram of every triangle at the smallest
+// Fused batch: the walk (threshold histogram of every triangle at the smallest
 // threshold) followed by edge-sampling units, in one persistent launch.
 __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __restrict__ o_off,
                                                const int32_t* __restrict__ o_adj,
@@ -291,31 +434,26 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
                                                const int64_t* __restrict__ n_items_dev,
                                                SampleParams sp, SampleGraph G,
                                                const int32_t* __restrict__ slen, int64_t units) {
-    __shared__ WalkLds lds[WPB];
+    __shared__ WalkShared S;
     __shared__ HistLds hlds[WPB];
     __shared__ SegLds slds[WPB];
     const int wib = threadIdx.x / UTRI_WAVE;
-    WalkLds& L = lds[wib];
     HistLds* H = &hlds[wib];
     for (int q = utri_lane(); q < 2 * NB; q += UTRI_WAVE) H->hist[q / NB][q % NB] = 0;
     utri_wave_sync();
-    const int64_t nitems = (wp.acc != nullptr) ? *n_items_dev : 0;
+    WalkLaneState st;
+    if (wp.acc != nullptr)
+        walk_phases<WALK_HIST>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
+                               n_items_dev[1], S, H, st);
     const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
     const int64_t W = (int64_t)gridDim.x * WPB;
     const int64_t upw = (sp.k + sp.chunk - 1) / sp.chunk;  // units per world
-    WalkLaneState st;
-    for (int64_t q = gw; q < nitems + units; q += W) {
-        if (q < nitems) {
-            const int64_t it = nitems - 1 - q;
-            walk_item<WALK_HIST>(wp, o_off, o_adj, o_d, len, perm, items[it], it, L, H, st);
-        } else {
-            const int64_t u = q - nitems;
-            const int32_t world = (int32_t)(u / upw);
-            const int64_t part = u % upw;
-            const int64_t i0 = part * sp.chunk;
-            const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
-            sample_unit(sp, G, slen, world, i0, i1, slds[wib]);
-        }
+    for (int64_t u = gw; u < units; u += W) {
+        const int32_t world = (int32_t)(u / upw);
+        const int64_t part = u % upw;
+        const int64_t i0 = part * sp.chunk;
+        const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
+        sample_unit(sp, G, slen, world, i0, i1, slds[wib]);
     }
     if (wp.acc != nullptr) walk_flush<WALK_HIST>(wp, H, st);
 }
@@ -326,31 +464,36 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
                       int64_t** n_items_dev, int32_t** len) {
     (void)cap;
     const int64_t n = g->n;
-    void *plen, *picnt, *pioff, *pitems, *pn;
+    const int64_t lb = light_bound(g), hb = heavy_bound(g);
+    void *plen, *pcnt, *poff, *pitems, *pn;
     UTRI_TRY(utri_scratch(g, SCR_LEN, sizeof(int32_t) * (size_t)(n + 1), &plen));
-    UTRI_TRY(utri_scratch(g, SCR_ICNT, sizeof(int32_t) * (size_t)(n + 1), &picnt));
-    UTRI_TRY(utri_scratch(g, SCR_IOFF, sizeof(int64_t) * (size_t)(n + 1), &pioff));
-    const int64_t bound = std::min<int64_t>(g->m, n + g->m / CAP + 1) + 1;
-    UTRI_TRY(utri_scratch(g, SCR_ITEMS, sizeof(int64_t) * (size_t)bound, &pitems));
+    UTRI_TRY(utri_scratch(g, SCR_ICNT, sizeof(int32_t) * (size_t)(2 * n + 2), &pcnt));
+    UTRI_TRY(utri_scratch(g, SCR_IOFF, sizeof(int64_t) * (size_t)(2 * n + 2), &poff));
+    UTRI_TRY(utri_scratch(g, SCR_ITEMS, sizeof(int64_t) * (size_t)(lb + hb), &pitems));
     UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 4, &pn));
     *items = (int64_t*)pitems;
     *n_items_dev = (int64_t*)pn;
     *len = (int32_t*)plen;
-    UTRI_TRY(utri_fill_u64(pn, 0, 1, s));
+    UTRI_TRY(utri_fill_u64(pn, 0, 2, s));
     if (n == 0) return UTRI_OK;
-    hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, n,
-                       c_rows, CAP, (int32_t*)plen, (int32_t*)picnt);
+    int32_t* lcnt = (int32_t*)pcnt;
+    int32_t* hcnt = lcnt + n;
+    int64_t* loff = (int64_t*)poff;
+    int64_t* hoff = loff + n;
+    hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, n, c_rows,
+                       (int32_t*)plen, lcnt, hcnt);
     UTRI_HIP_TRY(hipGetLastError());
-    UTRI_TRY(utri_scan_i32(g, (const int32_t*)picnt, (int64_t*)pioff, n, (int64_t*)pn, s));
-    hipLaunchKernelGGL(k_items, dim3(blocks_for(n)), dim3(TPB), 0, s, (const int32_t*)picnt,
-                       (const int64_t*)pioff, n, (int64_t*)pitems);
+    UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
+    UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
+    hipLaunchKernelGGL(k_items, dim3(blocks_for(n)), dim3(TPB), 0, s, (const int32_t*)lcnt,
+                       (const int32_t*)hcnt, (const int64_t*)loff, (const int64_t*)hoff, n, lb,
+                       (int64_t*)pitems);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }
 
-int utri_walk_items_bound(utri_graph* g) {
-    return (int)std::min<int64_t>(g->m, g->n + g->m / CAP + 1);
-}
+// Slots of the per-item enumeration arrays: one per light item, four per heavy item.
+int64_t utri_walk_items_bound(utri_graph* g) { return light_bound(g) + 4 * heavy_bound(g); }
 
 template <int MODE>
 static void launch_walk(utri_graph* g, int blocks, const WalkParams& wp, const int32_t* len,
@@ -359,11 +502,13 @@ static void launch_walk(utri_graph* g, int blocks, const WalkParams& wp, const i
                        g->o_d, len, g->perm, items, n_items_dev);
 }
 
-int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_t* items,
+int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int64_t* items,
                      const int64_t* n_items_dev, const int32_t* len, int64_t n_items_host_bound,
                      hipStream_t s) {
     (void)n_items_host_bound;
     if (g->n == 0 || g->m == 0) return UTRI_OK;
+    WalkParams wp = wp_in;
+    wp.lb = light_bound(g);
     const int blocks = g->num_cu * g->walk_blocks_per_cu;
     switch (mode) {
         case WALK_COUNT: launch_walk<WALK_COUNT>(g, blocks, wp, len, items, n_items_dev, s); break;
@@ -378,11 +523,13 @@ int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_
     return UTRI_OK;
 }
 
-int utri_batch_launch(utri_graph* g, const WalkParams& wp, const int64_t* items,
+int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* items,
                       const int64_t* n_items_dev, const int32_t* len, int64_t n_items_bound,
                       const SampleParams& sp, const int32_t* slen, hipStream_t s) {
     (void)n_items_bound;
     if (g->n == 0 || g->m == 0) return UTRI_OK;
+    WalkParams wp = wp_in;
+    wp.lb = light_bound(g);
     const int64_t units = (sp.hist != nullptr && sp.k > 0)
                               ? (int64_t)sp.worlds * ((sp.k + sp.chunk - 1) / sp.chunk) : 0;
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
