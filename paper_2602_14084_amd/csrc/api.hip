@@ -238,7 +238,7 @@ void apply_cache(utri_graph* g, const char* path) {
         if (!strstr(line, key.c_str())) continue;
         const char* a = strstr(line, "\"walk_blocks_per_cu\": ");
         const char* b = strstr(line, "\"sample_chunk\": ");
-        if (a) g->walk_blocks_per_cu = std::max(1, atoi(a + 22));
+        if (a) g->walk_blocks_per_cu = std::max(0, atoi(a + 22));
         if (b) g->sample_chunk = std::max(64, atoi(b + 16) / 64 * 64);
     }
     fclose(f);
@@ -273,6 +273,7 @@ int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int
     int rc = utri_load_internal(src, dst, p, m_in, n, ptr_kind, as_stream(hip_stream), &g);
     if (rc != UTRI_OK) return rc;
     apply_cache(g, getenv("UTRI_TUNE_CACHE"));
+    if (const char* e = getenv("UTRI_WALK_BLOCKS_PER_CU")) g->walk_blocks_per_cu = std::max(0, atoi(e));
     *out = g;
     return UTRI_OK;
 }
@@ -631,7 +632,8 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
     int64_t out[2];
     float best = 1e30f;
     int best_b = g->walk_blocks_per_cu;
-    for (int b : {1, 2, 3, 4, 6, 8}) {
+    // 0 = the kernel's resident occupancy; multiples of it trade tail balance for overhead
+    for (int b : {0, 3, 12, 18}) {
         g->walk_blocks_per_cu = b;
         UTRI_TRY(count_impl(g, t, UTRI_PRUNED, out, s));  // warm-up
         float tot = 0.f;

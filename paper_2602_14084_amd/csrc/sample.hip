@@ -135,7 +135,7 @@ static SampleGraph sample_graph(utri_graph* g) {
 int utri_sample_launch(utri_graph* g, const SampleParams& sp, const int32_t* slen, hipStream_t s) {
     if (g->m == 0 || sp.k <= 0 || sp.worlds <= 0) return UTRI_OK;
     const int64_t units = (int64_t)sp.worlds * ((sp.k + sp.chunk - 1) / sp.chunk);
-    const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * g->walk_blocks_per_cu,
+    const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * g->sample_blocks_per_cu,
                                               (units + WPB - 1) / WPB);
     hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(TPB), 0, s, sp, sample_graph(g), slen, units);
     UTRI_HIP_TRY(hipGetLastError());

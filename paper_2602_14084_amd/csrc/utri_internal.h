@@ -120,7 +120,8 @@ struct utri_graph {
     size_t scr_bytes[SCR_COUNT] = {};
 
     // launch shape (set by the autotuner, else defaults)
-    int walk_blocks_per_cu = 8;
+    int walk_blocks_per_cu = 0;     // 0: the kernel's resident occupancy
+    int sample_blocks_per_cu = 8;
     int sample_chunk = 2048;
 
     // event timing of the counting walk kernel (utri_timing)
@@ -304,6 +305,7 @@ struct WalkParams {
     int32_t* out_unbal = nullptr;
     int which = UTRI_BOTH;
     int64_t lb = 0;                     // first enumeration slot of the heavy items (set at launch)
+    unsigned long long* qctr = nullptr; // two work-queue counters, zeroed per launch
 };
 
 int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_t* items,

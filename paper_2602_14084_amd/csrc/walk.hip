@@ -28,6 +28,26 @@ namespace {
 constexpr int CAPH = 2048;         // source entries per work-group item
 constexpr int HSH = 2 * CAPH;      // work-group table slots
 
+#ifndef UTRI_WALK_UNR_MAX
+#define UTRI_WALK_UNR_MAX 4        // loads in flight per lane on long target rows
+#endif
+#ifndef UTRI_WALK_HASH24
+#define UTRI_WALK_HASH24 0         // 1: 24-bit multiplicative hash
+#endif
+#ifndef UTRI_WALK_DYNAMIC
+#define UTRI_WALK_DYNAMIC 1        // 1: items handed out by atomic work queues; 0: static stride
+#endif
+
+// slot of w in a 2^lg table of the walk
+__device__ __forceinline__ uint32_t walk_hash(int32_t w, int lg) {
+#if UTRI_WALK_HASH24
+    // __umul24 returns a signed int: shift the unsigned product, never the signed value
+    return (uint32_t)__umul24((uint32_t)w, 0x9E3779u) >> (32 - lg);
+#else
+    return utri_hash32(w, lg);
+#endif
+}
+
 inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
 
 struct BlockLds {
@@ -119,7 +139,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             bool is_b = false, is_u = false;
             int hit = -1;
             if (w[k] >= 0) {
-                uint32_t h = utri_hash32(w[k], R.lg);
+                uint32_t h = walk_hash(w[k], R.lg);
                 for (;;) {
                     const int kk = R.key[h];
                     if (kk == w[k]) { hit = R.pos[h]; break; }
@@ -187,6 +207,11 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* 
                                            int64_t ovs, int lvs, double duvs, int32_t pv,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
+#if UTRI_WALK_UNR_MAX >= 8
+    if (lvs > 4 * UTRI_WAVE)
+        stream_row<MODE, 8>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+    else
+#endif
     if (lvs > 2 * UTRI_WAVE)
         stream_row<MODE, 4>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
     else if (lvs > UTRI_WAVE)
@@ -230,7 +255,7 @@ __device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, i
     const uint32_t mask = (1u << lg) - 1u;
     for (int j = tid; j < cl; j += nthreads) {
         const int32_t w = o_adj[base + j];
-        uint32_t h = utri_hash32(w, lg);
+        uint32_t h = walk_hash(w, lg);
         for (;;) {
             const int old = atomicCAS(&key[h], -1, w);
             if (old == -1) { pos[h] = (uint16_t)j; break; }
@@ -386,6 +411,35 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
                             const int64_t* __restrict__ items, int64_t nl, int64_t nh,
                             WalkShared& S, HistLds* H, WalkLaneState& st) {
     const int wib = threadIdx.x / UTRI_WAVE;
+#if UTRI_WALK_DYNAMIC
+    // work queues: qctr[0] hands out heavy items to work-groups, qctr[1] light items to
+    // waves in groups of four
+    __shared__ int64_t s_q;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = (int64_t)atomicAdd(&wp.qctr[0], 1ull);
+        __syncthreads();
+        const int64_t q = s_q;
+        __syncthreads();
+        if (q >= nh) break;
+        const int64_t hq = nh - 1 - q;
+        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, S.block,
+                              H, st);
+    }
+    __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
+    constexpr int G = 4;
+    for (;;) {
+        int64_t base = 0;
+        if (utri_lane() == 0) base = (int64_t)atomicAdd(&wp.qctr[1], (unsigned long long)G);
+        base = bcast_i64(base, 0);
+        if (base >= nl) break;
+        const int64_t end = base + G < nl ? base + G : nl;
+        for (int64_t q = base; q < end; q++) {
+            const int64_t it = nl - 1 - q;
+            walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, (int)items[it], it,
+                                 S.wave[wib], H, st);
+        }
+    }
+#else
     for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
         const int64_t hq = nh - 1 - q;
         walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, S.block,
@@ -399,6 +453,7 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, (int)items[it], it, S.wave[wib], H,
                              st);
     }
+#endif
 }
 
 template <int MODE>
@@ -474,7 +529,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     *items = (int64_t*)pitems;
     *n_items_dev = (int64_t*)pn;
     *len = (int32_t*)plen;
-    UTRI_TRY(utri_fill_u64(pn, 0, 2, s));
+    UTRI_TRY(utri_fill_u64(pn, 0, 4, s));
     if (n == 0) return UTRI_OK;
     int32_t* lcnt = (int32_t*)pcnt;
     int32_t* hcnt = lcnt + n;
@@ -495,9 +550,21 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
 // Slots of the per-item enumeration arrays: one per light item, four per heavy item.
 int64_t utri_walk_items_bound(utri_graph* g) { return light_bound(g) + 4 * heavy_bound(g); }
 
+// Work-groups per CU for a kernel: the resident occupancy (so no second, partial round of
+// work-groups trails the statically strided items), unless a tuned value is set.
+template <class K>
+static int blocks_per_cu(utri_graph* g, K kernel) {
+    if (g->walk_blocks_per_cu > 0) return g->walk_blocks_per_cu;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, TPB, 0) != hipSuccess || nb < 1)
+        nb = 4;
+    return nb;
+}
+
 template <int MODE>
-static void launch_walk(utri_graph* g, int blocks, const WalkParams& wp, const int32_t* len,
+static void launch_walk(utri_graph* g, const WalkParams& wp, const int32_t* len,
                         const int64_t* items, const int64_t* n_items_dev, hipStream_t s) {
+    const int blocks = g->num_cu * blocks_per_cu(g, k_walk<MODE>);
     hipLaunchKernelGGL(k_walk<MODE>, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj,
                        g->o_d, len, g->perm, items, n_items_dev);
 }
@@ -509,14 +576,16 @@ int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int
     if (g->n == 0 || g->m == 0) return UTRI_OK;
     WalkParams wp = wp_in;
     wp.lb = light_bound(g);
-    const int blocks = g->num_cu * g->walk_blocks_per_cu;
+    // the work-queue counters live after the two item counts and restart at every launch
+    wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
+    UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     switch (mode) {
-        case WALK_COUNT: launch_walk<WALK_COUNT>(g, blocks, wp, len, items, n_items_dev, s); break;
-        case WALK_HIST: launch_walk<WALK_HIST>(g, blocks, wp, len, items, n_items_dev, s); break;
-        case WALK_EXPECTED: launch_walk<WALK_EXPECTED>(g, blocks, wp, len, items, n_items_dev, s); break;
-        case WALK_ENUM_COUNT: launch_walk<WALK_ENUM_COUNT>(g, blocks, wp, len, items, n_items_dev, s); break;
-        case WALK_ENUM_FILL: launch_walk<WALK_ENUM_FILL>(g, blocks, wp, len, items, n_items_dev, s); break;
-        case WALK_STATS: launch_walk<WALK_STATS>(g, blocks, wp, len, items, n_items_dev, s); break;
+        case WALK_COUNT: launch_walk<WALK_COUNT>(g, wp, len, items, n_items_dev, s); break;
+        case WALK_HIST: launch_walk<WALK_HIST>(g, wp, len, items, n_items_dev, s); break;
+        case WALK_EXPECTED: launch_walk<WALK_EXPECTED>(g, wp, len, items, n_items_dev, s); break;
+        case WALK_ENUM_COUNT: launch_walk<WALK_ENUM_COUNT>(g, wp, len, items, n_items_dev, s); break;
+        case WALK_ENUM_FILL: launch_walk<WALK_ENUM_FILL>(g, wp, len, items, n_items_dev, s); break;
+        case WALK_STATS: launch_walk<WALK_STATS>(g, wp, len, items, n_items_dev, s); break;
         default: return UTRI_E_INVALID;
     }
     UTRI_HIP_TRY(hipGetLastError());
@@ -530,11 +599,13 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     if (g->n == 0 || g->m == 0) return UTRI_OK;
     WalkParams wp = wp_in;
     wp.lb = light_bound(g);
+    wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
+    UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     const int64_t units = (sp.hist != nullptr && sp.k > 0)
                               ? (int64_t)sp.worlds * ((sp.k + sp.chunk - 1) / sp.chunk) : 0;
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
                   g->h_slot};
-    const int blocks = g->num_cu * g->walk_blocks_per_cu;
+    const int blocks = g->num_cu * blocks_per_cu(g, k_batch);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj, g->o_d,
                        len, g->perm, items, n_items_dev, sp, G, slen, units);
     UTRI_HIP_TRY(hipGetLastError());
