@@ -196,6 +196,20 @@ __global__ void k_scatter_oriented(const int32_t* __restrict__ oflag,
     o_eid[j] = s_eid[i];
 }
 
+// Pack sign(d) and a quantized |d| into the spare high bits of every oriented-row id.
+__global__ void k_pack_oriented(int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
+                                int64_t m, int idbits, int mb) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double d = o_d[i];
+    const uint32_t qmax = (1u << mb) - 2u;
+    uint32_t q = (uint32_t)(fabs(d) * (double)(1u << mb));  // floor: |d| >= q * 2^-mb
+    if (q > qmax) q = qmax;
+    const uint32_t sign = d < 0.0 ? 1u : 0u;
+    const uint32_t code = (sign << mb) | q;
+    o_adj[i] = (int32_t)(((uint32_t)o_adj[i]) | (code << idbits));
+}
+
 __global__ void k_oriented_offsets(const int64_t* __restrict__ s_off,
                                    const int64_t* __restrict__ opos,
                                    const int32_t* __restrict__ oflag, int64_t n, int64_t cnt,
@@ -386,6 +400,16 @@ int utri_build_rows(utri_graph* g, hipStream_t s) {
     hipLaunchKernelGGL(k_oriented_offsets, dim3(blocks_for(n + 1)), dim3(TPB), 0, s, g->s_off,
                        opos, oflag, n, cnt, g->o_off);
     UTRI_HIP_TRY(hipGetLastError());
+    // code bits of the oriented rows: sign + up to 15 magnitude bits above the id
+    g->idbits = (int)nbits;
+    g->idmask = (nbits >= 32) ? 0xFFFFFFFFu : ((1u << nbits) - 1u);
+    const int spare = 32 - (int)nbits;
+    g->code_mb = (spare >= 3) ? std::min(spare - 1, 15) : 0;
+    if (g->code_mb > 0) {
+        hipLaunchKernelGGL(k_pack_oriented, dim3(blocks_for(m)), dim3(TPB), 0, s, g->o_adj, g->o_d,
+                           m, g->idbits, g->code_mb);
+        UTRI_HIP_TRY(hipGetLastError());
+    }
     // hash tables
     int64_t* hs;
     UTRI_TRY(tmp_alloc(b7, n, &hs));

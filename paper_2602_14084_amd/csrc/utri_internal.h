@@ -110,9 +110,15 @@ struct utri_graph {
     int64_t h_total = 0;
 
     int64_t* o_off = nullptr;
-    int32_t* o_adj = nullptr;
+    int32_t* o_adj = nullptr;    // packed: id | (sign(d) << (idbits + mb) | q(|d|) << idbits)
     double* o_d = nullptr;
     int32_t* o_eid = nullptr;
+    // Oriented-row packing. Ids take the low `idbits` bits; when at least three bits are
+    // left, the high bits hold sign(d) and q = floor(|d| * 2^mb) (at most 2^mb - 2, the top
+    // bucket reaching 1), so |d| lies in [q, q + 1] * 2^-mb (the top bucket in [q * 2^-mb, 1]).
+    int idbits = 31;
+    int code_mb = 0;             // magnitude bits of the code, 0 = no code
+    uint32_t idmask = 0x7FFFFFFFu;
 
     uint32_t* d_flags = nullptr;
 
@@ -306,6 +312,12 @@ struct WalkParams {
     int which = UTRI_BOTH;
     int64_t lb = 0;                     // first enumeration slot of the heavy items (set at launch)
     unsigned long long* qctr = nullptr; // two work-queue counters, zeroed per launch
+    // oriented-row packing (set at launch from the graph) and float bounds of c:
+    // c_dn <= c <= c_up, both FP32
+    uint32_t idmask = 0x7FFFFFFFu;
+    int idbits = 31;
+    int mb = 0;
+    float c_up = 0.f, c_dn = 0.f;
 };
 
 int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_t* items,

@@ -117,7 +117,35 @@ struct RowCtx {
     int chunk;
 };
 
+// Decide a triangle from the exact d_uv and the codes of d_uw and d_vw, or report that
+// the codes cannot decide it. Each code bounds |d| to [q, q + 1] * 2^-mb (the top bucket
+// to [q * 2^-mb, 1]) and carries the exact sign. The bounds of the real product are
+// computed in FP32 and widened by a relative 2^-20 (covering the FP32 roundings and the
+// 2^-51 gap between the real product and the FP64 s of the exact rule) plus an absolute
+// 2^-100 (FP32 underflow); c_dn <= c <= c_up. Returns 1 balanced, 2 unbalanced,
+// 0 neither, -1 undecided.
+__device__ __forceinline__ int code_decide(const WalkParams& wp, double duv, uint32_t cu,
+                                           uint32_t cv) {
+    const uint32_t mmask = (1u << wp.mb) - 1u;
+    const uint32_t qtop = mmask - 1u;
+    const float scale = __uint_as_float((uint32_t)(127 - wp.mb) << 23);  // 2^-mb
+    const uint32_t qb = cu & mmask, qc = cv & mmask;
+    const float b0 = (float)qb * scale, b1 = (qb >= qtop) ? 1.0f : (float)(qb + 1u) * scale;
+    const float c0 = (float)qc * scale, c1 = (qc >= qtop) ? 1.0f : (float)(qc + 1u) * scale;
+    const float a = (float)fabs(duv);
+    const float mlo = (b0 * c0) * a * 0x1.ffffe0p-1f;              // * (1 - 2^-20)
+    const float mhi = (b1 * c1) * a * 0x1.000010p+0f + 0x1p-100f;  // * (1 + 2^-20) + 2^-100
+    const bool neg = (duv < 0.0) != (((cu ^ cv) >> wp.mb) & 1u);
+    const float slo = neg ? -mhi : mlo;
+    const float shi = neg ? -mlo : mhi;
+    if (shi <= -wp.c_up) return 1;
+    if (slo > wp.c_up) return 2;
+    if (slo > -wp.c_dn && shi <= wp.c_dn) return 0;
+    return -1;
+}
+
 // Stream the kept target row [ovs, ovs + lvs) of v, probing every entry in the table.
+// Row entries and table keys are packed words: id in the low bits, d code above.
 template <int MODE, int UNR>
 __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                            const double* __restrict__ o_d,
@@ -126,49 +154,63 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
     const int lane = utri_lane();
+    constexpr bool kCoded = (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
+                             MODE == WALK_ENUM_FILL);
+    const uint32_t* rowp = (const uint32_t*)o_adj + ovs;  // wave-uniform row base
+    const double* rowd = o_d + ovs;
     for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
-        int32_t w[UNR];
+        // all UNR loads are issued before any probe; lanes past the row end re-load its
+        // last entry (always in bounds) and drop the result below
+        uint32_t pw[UNR];
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;
-            w[k] = (j < lvs) ? o_adj[ovs + j] : -2;  // -2 matches no key and no empty slot
+            pw[k] = rowp[min(j, lvs - 1)];
         }
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;
+            const uint32_t w = pw[k] & wp.idmask;
             bool is_b = false, is_u = false;
-            int hit = -1;
-            if (w[k] >= 0) {
-                uint32_t h = walk_hash(w[k], R.lg);
-                for (;;) {
-                    const int kk = R.key[h];
-                    if (kk == w[k]) { hit = R.pos[h]; break; }
-                    if (kk == -1) break;
-                    h = (h + 1) & R.mask;
-                }
+            // linear probe until the key or an empty slot (-1, never a packed word); the
+            // empty test comes first because -1 & idmask can be a real id
+            uint32_t h = walk_hash((int32_t)w, R.lg);
+            int kk = R.key[h];
+            while (kk != -1 && ((uint32_t)kk & wp.idmask) != w) {
+                h = (h + 1) & R.mask;
+                kk = R.key[h];
             }
-            if (hit >= 0) {
-                const double dvw = o_d[ovs + j];
-                const double duw = o_d[R.src_base + hit];
+            if (j < lvs && kk != -1) {
+                const int hit = R.pos[h];
+                const uint32_t hkey = (uint32_t)kk;
                 if (MODE == WALK_STATS) {
                     st.tri++;
                 } else {
-                    const double s = utri_tri_s(duvs, duw, dvw);
+                    int dec = -1;
+                    if (kCoded && wp.mb > 0)
+                        dec = code_decide(wp, duvs, hkey >> wp.idbits, pw[k] >> wp.idbits);
+                    if (dec < 0) {
+                        const double s = utri_tri_s(duvs, o_d[R.src_base + hit], rowd[j]);
+                        dec = (s <= -wp.c) ? 1 : ((s > wp.c) ? 2 : 0);
+                        if (!kCoded) {
+                            if (MODE == WALK_HIST) {
+                                bool bal;
+                                const int bin = utri_bin_of(s, wp.cvals, wp.nt, bal);
+                                if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
+                            } else if (MODE == WALK_EXPECTED) {
+                                const int64_t t = utri_fix62(s);
+                                st.tri++;
+                                st.slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
+                                st.shi += (t >> 32);
+                            }
+                        }
+                    }
                     if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) {
-                        if (s <= -wp.c) st.nb++;
-                        else if (s > wp.c) st.nu++;
-                    } else if (MODE == WALK_HIST) {
-                        bool bal;
-                        const int bin = utri_bin_of(s, wp.cvals, wp.nt, bal);
-                        if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
-                    } else if (MODE == WALK_EXPECTED) {
-                        const int64_t t = utri_fix62(s);
-                        st.tri++;
-                        st.slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
-                        st.shi += (t >> 32);
+                        if (dec == 1) st.nb++;
+                        else if (dec == 2) st.nu++;
                     } else if (MODE == WALK_ENUM_FILL) {
-                        is_b = (s <= -wp.c) && (wp.which & UTRI_BAL);
-                        is_u = (s > wp.c) && (wp.which & UTRI_UNBAL);
+                        is_b = (dec == 1) && (wp.which & UTRI_BAL);
+                        is_u = (dec == 2) && (wp.which & UTRI_UNBAL);
                     }
                 }
             }
@@ -176,7 +218,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                 const uint64_t mb = __ballot(is_b);
                 const uint64_t mu = __ballot(is_u);
                 if (is_b || is_u) {
-                    int32_t a = R.pu, b = pv, c = perm[w[k]], t;
+                    int32_t a = R.pu, b = pv, c = perm[w], t;
                     if (b < a) { t = a; a = b; b = t; }
                     if (c < b) { t = b; b = c; c = t; }
                     if (b < a) { t = a; a = b; b = t; }
@@ -230,7 +272,7 @@ __device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t
     const int i = i0 + utri_lane();
     lv = 0; v = 0; ov = 0; duv = 0.0;
     if (i < Lu) {
-        v = o_adj[ou + i];
+        v = (int)((uint32_t)o_adj[ou + i] & wp.idmask);
         duv = o_d[ou + i];
         ov = o_off[v];
         lv = len[v];
@@ -251,13 +293,14 @@ __device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t
 // 2^lg slots; `tid` / `nthreads` are the caller's lanes (one wave or one work-group).
 __device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, int64_t base, int cl,
                                             int32_t* key, uint16_t* pos, int lg, int tid,
-                                            int nthreads) {
+                                            int nthreads, uint32_t idmask) {
     const uint32_t mask = (1u << lg) - 1u;
     for (int j = tid; j < cl; j += nthreads) {
-        const int32_t w = o_adj[base + j];
-        uint32_t h = walk_hash(w, lg);
+        // the key is the packed word (id and d code); it is never -1, the empty marker
+        const int32_t pw = o_adj[base + j];
+        uint32_t h = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
         for (;;) {
-            const int old = atomicCAS(&key[h], -1, w);
+            const int old = atomicCAS(&key[h], -1, pw);
             if (old == -1) { pos[h] = (uint16_t)j; break; }
             h = (h + 1) & mask;
         }
@@ -283,7 +326,7 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const int size = 1 << lg;
     for (int i = lane; i < size; i += UTRI_WAVE) L.key[i] = -1;
     utri_wave_sync();
-    stage_table(o_adj, ou, Lu, L.key, L.pos, lg, lane, UTRI_WAVE);
+    stage_table(o_adj, ou, Lu, L.key, L.pos, lg, lane, UTRI_WAVE, wp.idmask);
     utri_wave_sync();
     RowCtx R{L.key, L.pos, lg, (uint32_t)(size - 1), ou,
              (MODE == WALK_ENUM_FILL) ? perm[u] : 0, 0};
@@ -333,7 +376,7 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     __syncthreads();  // the previous item's probes are done
     for (int i = threadIdx.x; i < size; i += TPB) B.key[i] = -1;
     __syncthreads();
-    stage_table(o_adj, ou + cb, cl, B.key, B.pos, lg, threadIdx.x, TPB);
+    stage_table(o_adj, ou + cb, cl, B.key, B.pos, lg, threadIdx.x, TPB, wp.idmask);
     __syncthreads();
     RowCtx R{B.key, B.pos, lg, (uint32_t)(size - 1), ou + cb,
              (MODE == WALK_ENUM_FILL) ? perm[u] : 0, chunk};
@@ -547,6 +590,19 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     return UTRI_OK;
 }
 
+// Graph-dependent fields of a launch: enumeration slot base, row packing, FP32 bounds of c.
+static void set_launch_fields(utri_graph* g, WalkParams& wp) {
+    wp.lb = light_bound(g);
+    wp.idmask = g->idmask;
+    wp.idbits = g->idbits;
+    wp.mb = g->code_mb;
+    float up = (float)wp.c, dn = (float)wp.c;
+    if ((double)up < wp.c) up = nextafterf(up, INFINITY);
+    if ((double)dn > wp.c) dn = nextafterf(dn, -INFINITY);
+    wp.c_up = up;
+    wp.c_dn = dn;
+}
+
 // Slots of the per-item enumeration arrays: one per light item, four per heavy item.
 int64_t utri_walk_items_bound(utri_graph* g) { return light_bound(g) + 4 * heavy_bound(g); }
 
@@ -575,7 +631,7 @@ int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int
     (void)n_items_host_bound;
     if (g->n == 0 || g->m == 0) return UTRI_OK;
     WalkParams wp = wp_in;
-    wp.lb = light_bound(g);
+    set_launch_fields(g, wp);
     // the work-queue counters live after the two item counts and restart at every launch
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
@@ -598,7 +654,7 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     (void)n_items_bound;
     if (g->n == 0 || g->m == 0) return UTRI_OK;
     WalkParams wp = wp_in;
-    wp.lb = light_bound(g);
+    set_launch_fields(g, wp);
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     const int64_t units = (sp.hist != nullptr && sp.k > 0)
