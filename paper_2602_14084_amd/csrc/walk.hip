@@ -117,30 +117,48 @@ struct RowCtx {
     int chunk;
 };
 
-// Decide a triangle from the exact d_uv and the codes of d_uw and d_vw, or report that
-// the codes cannot decide it. Each code bounds |d| to [q, q + 1] * 2^-mb (the top bucket
-// to [q * 2^-mb, 1]) and carries the exact sign. The bounds of the real product are
-// computed in FP32 and widened by a relative 2^-20 (covering the FP32 roundings and the
-// 2^-51 gap between the real product and the FP64 s of the exact rule) plus an absolute
-// 2^-100 (FP32 underflow); c_dn <= c <= c_up. Returns 1 balanced, 2 unbalanced,
-// 0 neither, -1 undecided.
-__device__ __forceinline__ int code_decide(const WalkParams& wp, double duv, uint32_t cu,
+// Per-row integer thresholds of the code decision. With A = |d_uv| and code magnitudes
+// qb (of d_uw) and qc (of d_vw), |s| lies in [A * P0, A * P1] * 2^-2mb with P0 = qb * qc and
+// P1 = qb' * qc' (q' = q + 1, or 2^mb for the top bucket). With K = c * 2^2mb / A:
+//   P0 >= khi = floor(K (1 + 2^-40)) + 1   =>  |s| > c  (balanced if s < 0, else unbalanced)
+//   P1 <= klo = floor(K (1 - 2^-40))       =>  |s| < c  (neither)
+// The 2^-40 margins exceed the roundings of K and the 2^-51 gap between the real product
+// and the FP64 s of the exact rule. A = 0 rows are left to the exact rule.
+struct CodeRow {
+    uint32_t khi, klo;
+    bool neg_a;
+};
+
+__device__ __forceinline__ CodeRow code_row(const WalkParams& wp, double duv) {
+    CodeRow r;
+    const double a = fabs(duv);
+    r.neg_a = duv < 0.0;
+    if (!(a > 0.0) || wp.mb == 0) {
+        r.khi = 0xFFFFFFFFu;
+        r.klo = 0u;
+        return r;
+    }
+    const double K = ldexp(wp.c, 2 * wp.mb) / a;
+    const double hi = floor(K * (1.0 + 0x1p-40)) + 1.0;
+    const double lo = floor(K * (1.0 - 0x1p-40));
+    r.khi = hi >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)hi;
+    r.klo = lo >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)lo;
+    return r;
+}
+
+// 1 balanced, 2 unbalanced, 0 neither, -1 undecided (see code_row)
+__device__ __forceinline__ int code_decide(const WalkParams& wp, const CodeRow& r, uint32_t cu,
                                            uint32_t cv) {
     const uint32_t mmask = (1u << wp.mb) - 1u;
     const uint32_t qtop = mmask - 1u;
-    const float scale = __uint_as_float((uint32_t)(127 - wp.mb) << 23);  // 2^-mb
     const uint32_t qb = cu & mmask, qc = cv & mmask;
-    const float b0 = (float)qb * scale, b1 = (qb >= qtop) ? 1.0f : (float)(qb + 1u) * scale;
-    const float c0 = (float)qc * scale, c1 = (qc >= qtop) ? 1.0f : (float)(qc + 1u) * scale;
-    const float a = (float)fabs(duv);
-    const float mlo = (b0 * c0) * a * 0x1.ffffe0p-1f;              // * (1 - 2^-20)
-    const float mhi = (b1 * c1) * a * 0x1.000010p+0f + 0x1p-100f;  // * (1 + 2^-20) + 2^-100
-    const bool neg = (duv < 0.0) != (((cu ^ cv) >> wp.mb) & 1u);
-    const float slo = neg ? -mhi : mlo;
-    const float shi = neg ? -mlo : mhi;
-    if (shi <= -wp.c_up) return 1;
-    if (slo > wp.c_up) return 2;
-    if (slo > -wp.c_dn && shi <= wp.c_dn) return 0;
+    const uint32_t qb1 = qb >= qtop ? mmask + 1u : qb + 1u;
+    const uint32_t qc1 = qc >= qtop ? mmask + 1u : qc + 1u;
+    // operands are below 2^16: the 24-bit multiplier is exact (its result is a signed int)
+    const uint32_t p0 = (uint32_t)__umul24(qb, qc), p1 = (uint32_t)__umul24(qb1, qc1);
+    const bool neg = r.neg_a != (((cu ^ cv) >> wp.mb) & 1u);
+    if (p0 >= r.khi) return neg ? 1 : 2;
+    if (p1 <= r.klo) return 0;
     return -1;
 }
 
@@ -150,12 +168,15 @@ template <int MODE, int UNR>
 __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                            const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const RowCtx& R,
-                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv, const CodeRow& cr,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
     const int lane = utri_lane();
-    constexpr bool kCoded = (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
-                             MODE == WALK_ENUM_FILL);
+#ifndef UTRI_WALK_CODES
+#define UTRI_WALK_CODES 1
+#endif
+    constexpr bool kCoded = UTRI_WALK_CODES && (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
+                                                MODE == WALK_ENUM_FILL);
     const uint32_t* rowp = (const uint32_t*)o_adj + ovs;  // wave-uniform row base
     const double* rowd = o_d + ovs;
     for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
@@ -188,7 +209,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                 } else {
                     int dec = -1;
                     if (kCoded && wp.mb > 0)
-                        dec = code_decide(wp, duvs, hkey >> wp.idbits, pw[k] >> wp.idbits);
+                        dec = code_decide(wp, cr, hkey >> wp.idbits, pw[k] >> wp.idbits);
                     if (dec < 0) {
                         const double s = utri_tri_s(duvs, o_d[R.src_base + hit], rowd[j]);
                         dec = (s <= -wp.c) ? 1 : ((s > wp.c) ? 2 : 0);
@@ -246,20 +267,20 @@ template <int MODE>
 __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                            const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const RowCtx& R,
-                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv, const CodeRow& cr,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
 #if UTRI_WALK_UNR_MAX >= 8
     if (lvs > 4 * UTRI_WAVE)
-        stream_row<MODE, 8>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+        stream_row<MODE, 8>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
     else
 #endif
     if (lvs > 2 * UTRI_WAVE)
-        stream_row<MODE, 4>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+        stream_row<MODE, 4>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
     else if (lvs > UTRI_WAVE)
-        stream_row<MODE, 2>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+        stream_row<MODE, 2>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
     else
-        stream_row<MODE, 1>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, H, st, run_b, run_u);
+        stream_row<MODE, 1>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
 }
 
 // Load, on lane i, v = N+(u)[i0 + i] with its row start, kept length and d_uv.
@@ -268,9 +289,10 @@ __device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t
                                              const double* __restrict__ o_d,
                                              const int32_t* __restrict__ len, int64_t ou, int Lu,
                                              int i0, double dmax_chunk, int& v, int64_t& ov,
-                                             int& lv, double& duv) {
+                                             int& lv, double& duv, CodeRow& cr) {
     const int i = i0 + utri_lane();
     lv = 0; v = 0; ov = 0; duv = 0.0;
+    cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.neg_a = false;
     if (i < Lu) {
         v = (int)((uint32_t)o_adj[ou + i] & wp.idmask);
         duv = o_d[ou + i];
@@ -286,6 +308,7 @@ __device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t
             }
             lv = a;
         }
+        cr = code_row(wp, duv);
     }
 }
 
@@ -337,14 +360,18 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
         int v, lv;
         int64_t ov;
         double duv;
-        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv);
+        CodeRow cr;
+        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv, cr);
         const int nv = min(UTRI_WAVE, Lu - i0);
         for (int si = 0; si < nv; si++) {
             const int lvs = bcast_i32(lv, si);
             if (lvs == 0) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)] : 0;
+            const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
+                              (uint32_t)bcast_i32((int)cr.klo, si),
+                              bcast_i32(cr.neg_a ? 1 : 0, si) != 0};
             stream_any<MODE>(wp, o_adj, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
-                             pv, H, st, run_b, run_u);
+                             pv, crs, H, st, run_b, run_u);
         }
     }
     if (MODE == WALK_ENUM_COUNT) {
@@ -388,14 +415,18 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
         int v, lv;
         int64_t ov;
         double duv;
-        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv);
+        CodeRow cr;
+        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv, cr);
         const int nv = min(UTRI_WAVE, Lu - i0);
         for (int si = wib; si < nv; si += WPB) {
             const int lvs = bcast_i32(lv, si);
             if (lvs == 0) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)] : 0;
+            const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
+                              (uint32_t)bcast_i32((int)cr.klo, si),
+                              bcast_i32(cr.neg_a ? 1 : 0, si) != 0};
             stream_any<MODE>(wp, o_adj, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
-                             pv, H, st, run_b, run_u);
+                             pv, crs, H, st, run_b, run_u);
         }
     }
     if (MODE == WALK_ENUM_COUNT) {
