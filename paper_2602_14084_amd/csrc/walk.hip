@@ -25,8 +25,11 @@ using namespace utri_dev;
 
 namespace {
 
-constexpr int CAPH = 2048;         // source entries per work-group item
-constexpr int HSH = 2 * CAPH;      // work-group table slots
+#ifndef UTRI_WALK_CAPH
+#define UTRI_WALK_CAPH 1024
+#endif
+constexpr int CAPH = UTRI_WALK_CAPH;  // source entries per work-group item
+constexpr int HSH = 2 * CAPH;         // work-group table slots
 
 #ifndef UTRI_WALK_UNR_MAX
 #define UTRI_WALK_UNR_MAX 4        // loads in flight per lane on long target rows
@@ -59,7 +62,7 @@ union WalkShared {
     WalkLds wave[WPB];
     BlockLds block;
 };
-static_assert(sizeof(BlockLds) <= sizeof(WalkLds) * WPB, "work-group table must fit the wave tables");
+static_assert(CAPH >= CAP && CAPH <= 65536, "work-group chunks hold every long row's chunk");
 
 // Bounds of the two item lists: light items (one per source row with 2 <= len <= CAP)
 // and heavy items (len > CAP, ceil(len / CAPH) chunks per row).
@@ -500,12 +503,22 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
                               H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
-    constexpr int G = 4;
+#ifndef UTRI_WALK_QGROUP
+#define UTRI_WALK_QGROUP 4
+#endif
+#ifndef UTRI_WALK_QGROW
+#define UTRI_WALK_QGROW 0   // > 0: grab 1 + QGROW * (position / nl) items (lighter items later)
+#endif
+    int64_t last = 0;
     for (;;) {
+        const int G = UTRI_WALK_QGROW > 0
+                          ? 1 + (int)((last * UTRI_WALK_QGROW) / (nl > 0 ? nl : 1))
+                          : UTRI_WALK_QGROUP;
         int64_t base = 0;
         if (utri_lane() == 0) base = (int64_t)atomicAdd(&wp.qctr[1], (unsigned long long)G);
         base = bcast_i64(base, 0);
         if (base >= nl) break;
+        last = base;
         const int64_t end = base + G < nl ? base + G : nl;
         for (int64_t q = base; q < end; q++) {
             const int64_t it = nl - 1 - q;

@@ -8,8 +8,11 @@ namespace utri_dev {
 
 constexpr int TPB = 256;
 constexpr int WPB = TPB / UTRI_WAVE;
-constexpr int CAP = 512;       // hash-side entries per walk item
-constexpr int HS = 2 * CAP;    // LDS table slots (load factor <= 1/2)
+#ifndef UTRI_WALK_CAP
+#define UTRI_WALK_CAP 256
+#endif
+constexpr int CAP = UTRI_WALK_CAP;  // longest source row staged by one wave
+constexpr int HS = 2 * CAP;         // LDS table slots (load factor <= 1/2)
 constexpr int NB = 65;         // histogram bins (nt + 1 <= 65)
 
 // LDS of one wave of the walk: the staged source chunk as an open-addressing table
