@@ -72,6 +72,10 @@ enum UtriScratch {
     SCR_OUT,          // int64 small device results
     SCR_SEED,         // u64 seed of the captured batch
     SCR_HIST2,        // u64 walk histogram of the batch
+    SCR_GCNT,         // int32 [3n] gradient items per owner (wave, work-group, hub)
+    SCR_GOFF,         // int64 [3n] gradient item offsets
+    SCR_GITEMS,       // int64 gradient items
+    SCR_GQ,           // int64 [16] gradient item counts and work-queue counters
     SCR_COUNT
 };
 

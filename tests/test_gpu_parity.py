@@ -165,6 +165,26 @@ def test_grad_matches_oracle_exactly():
             assert np.array_equal(got, og.grad()), name
 
 
+def test_grad_hub_rows_match_oracle():
+    # owners of every class: rows staged by one wave, by one work-group, and hub rows
+    # probed through their global tables (degree above 4096)
+    n, lo, hi = inputs.rmat_graph(15, seed=3)
+    deg = np.bincount(np.concatenate([lo, hi]), minlength=n)
+    assert deg.max() > 4096 and (deg > 2048).sum() > 8
+    p = inputs.draw_p(lo.shape[0], "uniform_05_95", 41)
+    og = oracle.load(n, lo, hi, p)
+    say("grad", "rmat15", "max deg", int(deg.max()))
+    g = gpu_graph(n, lo, hi, p)
+    got = g.expected_grad().cpu().numpy()
+    assert np.array_equal(got, og.grad())
+    # a second call reuses the handle's item buffers and queues
+    assert np.array_equal(g.expected_grad().cpu().numpy(), got)
+    # new probabilities: the hub tables carry d values and must follow them
+    p2 = inputs.draw_p(lo.shape[0], "beta0505", 43)
+    g.set_p(p2)
+    assert np.array_equal(g.expected_grad().cpu().numpy(), oracle.load(n, lo, hi, p2).grad())
+
+
 def test_autograd_function_and_set_p():
     n, lo, hi = inputs.chung_lu_graph(500, 2.5, 4000.0, 12)
     p0 = inputs.draw_p(lo.shape[0], "uniform", 1)
