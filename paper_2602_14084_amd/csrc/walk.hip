@@ -29,7 +29,7 @@ namespace {
 #define UTRI_WALK_CAPH 1024
 #endif
 constexpr int CAPH = UTRI_WALK_CAPH;  // source entries per work-group item
-constexpr int HSH = 2 * CAPH;         // work-group table slots
+constexpr int HSH = SLOTS * CAPH;     // work-group table slots (buckets of 4)
 
 #ifndef UTRI_WALK_UNR_MAX
 #define UTRI_WALK_UNR_MAX 4        // loads in flight per lane on long target rows
@@ -54,7 +54,7 @@ __device__ __forceinline__ uint32_t walk_hash(int32_t w, int lg) {
 inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
 
 struct BlockLds {
-    int32_t key[HSH];
+    alignas(16) int32_t key[HSH];
     uint16_t pos[HSH];
 };
 
@@ -62,7 +62,8 @@ union WalkShared {
     WalkLds wave[WPB];
     BlockLds block;
 };
-static_assert(CAPH >= CAP && CAPH <= 65536, "work-group chunks hold every long row's chunk");
+static_assert(CAPH >= CAP && CAPH <= 65536 && (CAPH & (CAPH - 1)) == 0,
+              "work-group chunks hold every long row's chunk; table sizes are powers of two");
 
 // Bounds of the two item lists: light items (one per source row with 2 <= len <= CAP)
 // and heavy items (len > CAP, ceil(len / CAPH) chunks per row).
@@ -111,10 +112,10 @@ struct WalkLaneState {
 
 // The staged source chunk and the current pair (u, v).
 struct RowCtx {
-    const int32_t* key;
+    const int32_t* key;  // 2^lg buckets of 4 slots; slots of a bucket fill in order
     const uint16_t* pos;
     int lg;
-    uint32_t mask;
+    uint32_t mask;       // bucket index mask
     int64_t src_base;   // o_off[u] + chunk start: position of hash hits in o_adj / o_d
     int32_t pu;         // perm[u] (enumeration)
     int chunk;
@@ -158,11 +159,13 @@ __device__ __forceinline__ int code_decide(const WalkParams& wp, const CodeRow& 
     const uint32_t qb1 = qb >= qtop ? mmask + 1u : qb + 1u;
     const uint32_t qc1 = qc >= qtop ? mmask + 1u : qc + 1u;
     // operands are below 2^16: the 24-bit multiplier is exact (its result is a signed int)
-    const uint32_t p0 = (uint32_t)__umul24(qb, qc), p1 = (uint32_t)__umul24(qb1, qc1);
-    const bool neg = r.neg_a != (((cu ^ cv) >> wp.mb) & 1u);
-    if (p0 >= r.khi) return neg ? 1 : 2;
-    if (p1 <= r.klo) return 0;
-    return -1;
+    uint32_t p0 = (uint32_t)__umul24(qb, qc), p1 = (uint32_t)__umul24(qb1, qc1);
+    // both products in registers first, so the selects below stay selects (the caller
+    // evaluates this on every lane; branches would only add exec-mask work)
+    asm volatile("" : "+v"(p0), "+v"(p1));
+    const int neg = (int)((r.neg_a ? 1u : 0u) ^ (((cu ^ cv) >> wp.mb) & 1u));
+    const int dec = (p1 <= r.klo) ? 0 : -1;
+    return (p0 >= r.khi) ? 2 - neg : dec;
 }
 
 // Stream the kept target row [ovs, ovs + lvs) of v, probing every entry in the table.
@@ -171,7 +174,8 @@ template <int MODE, int UNR>
 __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                            const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const RowCtx& R,
-                                           int64_t ovs, int lvs, double duvs, int32_t pv, const CodeRow& cr,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           const CodeRow& cr,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
     const int lane = utri_lane();
@@ -196,16 +200,26 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             const int j = j0 + k * UTRI_WAVE + lane;
             const uint32_t w = pw[k] & wp.idmask;
             bool is_b = false, is_u = false;
-            // linear probe until the key or an empty slot (-1, never a packed word); the
-            // empty test comes first because -1 & idmask can be a real id
-            uint32_t h = walk_hash((int32_t)w, R.lg);
-            int kk = R.key[h];
-            while (kk != -1 && ((uint32_t)kk & wp.idmask) != w) {
-                h = (h + 1) & R.mask;
-                kk = R.key[h];
+            // linear probe over 4-slot buckets until the key or a bucket with an empty
+            // slot (-1, never a packed word; tested first because -1 & idmask can be a
+            // real id). Slots of a bucket fill in order, so its last slot tells.
+            uint32_t b = walk_hash((int32_t)w, R.lg);
+            int kk, h;
+            for (;;) {
+                const int4 kv = *reinterpret_cast<const int4*>(R.key + 4 * b);
+                const bool f0 = kv.x != -1 && ((uint32_t)kv.x & wp.idmask) == w;
+                const bool f1 = kv.y != -1 && ((uint32_t)kv.y & wp.idmask) == w;
+                const bool f2 = kv.z != -1 && ((uint32_t)kv.z & wp.idmask) == w;
+                const bool f3 = kv.w != -1 && ((uint32_t)kv.w & wp.idmask) == w;
+                kk = f0 ? kv.x : f1 ? kv.y : f2 ? kv.z : f3 ? kv.w : -1;
+                h = 4 * (int)b + (f0 ? 0 : f1 ? 1 : f2 ? 2 : 3);
+                // keep the results in registers here: otherwise the compiler carries the
+                // four match flags out of the loop as scalar lane masks
+                asm volatile("" : "+v"(kk), "+v"(h));
+                if (kk != -1 || kv.w == -1) break;
+                b = (b + 1) & R.mask;
             }
             if (j < lvs && kk != -1) {
-                const int hit = R.pos[h];
                 const uint32_t hkey = (uint32_t)kk;
                 if (MODE == WALK_STATS) {
                     st.tri++;
@@ -214,6 +228,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                     if (kCoded && wp.mb > 0)
                         dec = code_decide(wp, cr, hkey >> wp.idbits, pw[k] >> wp.idbits);
                     if (dec < 0) {
+                        const int hit = R.pos[h];  // only the exact rule reads d_uw
                         const double s = utri_tri_s(duvs, o_d[R.src_base + hit], rowd[j]);
                         dec = (s <= -wp.c) ? 1 : ((s > wp.c) ? 2 : 0);
                         if (!kCoded) {
@@ -270,7 +285,8 @@ template <int MODE>
 __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                            const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const RowCtx& R,
-                                           int64_t ovs, int lvs, double duvs, int32_t pv, const CodeRow& cr,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           const CodeRow& cr,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
 #if UTRI_WALK_UNR_MAX >= 8
@@ -316,7 +332,9 @@ __device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t
 }
 
 // Stage `cl` source entries starting at o_adj[base] into an open-addressing table of
-// 2^lg slots; `tid` / `nthreads` are the caller's lanes (one wave or one work-group).
+// 2^lg buckets of 4 slots; `tid` / `nthreads` are the caller's lanes (one wave or one
+// work-group). Each entry takes the first free slot of the first bucket (from its home
+// bucket on) that has one; slots are claimed in order, so a bucket's slots fill in order.
 __device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, int64_t base, int cl,
                                             int32_t* key, uint16_t* pos, int lg, int tid,
                                             int nthreads, uint32_t idmask) {
@@ -324,18 +342,20 @@ __device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, i
     for (int j = tid; j < cl; j += nthreads) {
         // the key is the packed word (id and d code); it is never -1, the empty marker
         const int32_t pw = o_adj[base + j];
-        uint32_t h = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
+        uint32_t b = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
         for (;;) {
-            const int old = atomicCAS(&key[h], -1, pw);
-            if (old == -1) { pos[h] = (uint16_t)j; break; }
-            h = (h + 1) & mask;
+            int s = 0;
+            while (s < 4 && atomicCAS(&key[4 * b + s], -1, pw) != -1) s++;
+            if (s < 4) { pos[4 * b + s] = (uint16_t)j; break; }
+            b = (b + 1) & mask;
         }
     }
 }
 
+// log2 of the bucket count of a table for cl entries: 4 * 2^lg >= SLOTS * cl, 2^lg >= 2
 __device__ __forceinline__ int table_lg(int cl) {
     int lg = 1;
-    while ((1 << lg) < 2 * cl) lg++;
+    while ((4 << lg) < SLOTS * cl) lg++;
     return lg;
 }
 
@@ -349,12 +369,12 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const int64_t ou = o_off[u];
     const int Lu = len[u];
     const int lg = table_lg(Lu);
-    const int size = 1 << lg;
-    for (int i = lane; i < size; i += UTRI_WAVE) L.key[i] = -1;
+    const int nbk = 1 << lg;  // buckets
+    for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) L.key[i] = -1;
     utri_wave_sync();
     stage_table(o_adj, ou, Lu, L.key, L.pos, lg, lane, UTRI_WAVE, wp.idmask);
     utri_wave_sync();
-    RowCtx R{L.key, L.pos, lg, (uint32_t)(size - 1), ou,
+    RowCtx R{L.key, L.pos, lg, (uint32_t)(nbk - 1), ou,
              (MODE == WALK_ENUM_FILL) ? perm[u] : 0, 0};
     const double dmax_chunk = fabs(o_d[ou]);
     int64_t run_b = 0, run_u = 0;
@@ -402,13 +422,13 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     const int cb = chunk * CAPH;
     const int cl = min(CAPH, Lu - cb);
     const int lg = table_lg(cl);
-    const int size = 1 << lg;
+    const int nbk = 1 << lg;  // buckets
     __syncthreads();  // the previous item's probes are done
-    for (int i = threadIdx.x; i < size; i += TPB) B.key[i] = -1;
+    for (int i = threadIdx.x; i < 4 * nbk; i += TPB) B.key[i] = -1;
     __syncthreads();
     stage_table(o_adj, ou + cb, cl, B.key, B.pos, lg, threadIdx.x, TPB, wp.idmask);
     __syncthreads();
-    RowCtx R{B.key, B.pos, lg, (uint32_t)(size - 1), ou + cb,
+    RowCtx R{B.key, B.pos, lg, (uint32_t)(nbk - 1), ou + cb,
              (MODE == WALK_ENUM_FILL) ? perm[u] : 0, chunk};
     const double dmax_chunk = fabs(o_d[ou + cb]);
     const int64_t slot = wp.lb + 4 * hq + wib;
@@ -440,7 +460,8 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
 }
 
 template <int MODE>
-__device__ void walk_flush(const WalkParams& wp, HistLds* H, WalkLaneState& st) {
+__device__ void walk_flush(const WalkParams& wp, const double* __restrict__ o_d, HistLds* H,
+                           WalkLaneState& st) {
     const int lane = utri_lane();
     if (MODE == WALK_COUNT) {
         const uint64_t b = utri_wave_sum_u64(st.nb), u = utri_wave_sum_u64(st.nu);
@@ -562,7 +583,7 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
     WalkLaneState st;
     walk_phases<MODE>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0], n_items_dev[1], S,
                       H, st);
-    walk_flush<MODE>(wp, H, st);
+    walk_flush<MODE>(wp, o_d, H, st);
 }
 
 // Fused batch: the walk (threshold histogram of every triangle at the smallest
@@ -597,7 +618,7 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
         const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
         sample_unit(sp, G, slen, world, i0, i1, slds[wib]);
     }
-    if (wp.acc != nullptr) walk_flush<WALK_HIST>(wp, H, st);
+    if (wp.acc != nullptr) walk_flush<WALK_HIST>(wp, o_d, H, st);
 }
 
 }  // namespace

@@ -11,13 +11,22 @@ constexpr int WPB = TPB / UTRI_WAVE;
 #ifndef UTRI_WALK_CAP
 #define UTRI_WALK_CAP 256
 #endif
+#ifndef UTRI_WALK_SLOTS
+#define UTRI_WALK_SLOTS 4
+#endif
 constexpr int CAP = UTRI_WALK_CAP;  // longest source row staged by one wave
-constexpr int HS = 2 * CAP;         // LDS table slots (load factor <= 1/2)
+constexpr int SLOTS = UTRI_WALK_SLOTS;  // table slots per staged entry (load factor 1/SLOTS)
+constexpr int HS = SLOTS * CAP;     // LDS table slots, in buckets of 4
+// a table for cl <= CAP entries has the least power-of-two bucket count with 4 * buckets
+// >= SLOTS * cl (at least 2 buckets): with powers of two that is at most HS slots
+static_assert((CAP & (CAP - 1)) == 0 && (SLOTS & (SLOTS - 1)) == 0 && SLOTS * CAP >= 8,
+              "table sizes are powers of two");
 constexpr int NB = 65;         // histogram bins (nt + 1 <= 65)
 
-// LDS of one wave of the walk: the staged source chunk as an open-addressing table
+// LDS of one wave of the walk: the staged source chunk as an open-addressing table of
+// 4-slot buckets (one 16-byte LDS read per bucket)
 struct WalkLds {
-    int32_t key[HS];
+    alignas(16) int32_t key[HS];
     uint16_t pos[HS];
 };
 
