@@ -7,16 +7,19 @@
 // reduces each row to a prefix of length len[x]; the optional Lemma-3 cut shortens the
 // target row N+(v) further, per pair, to entries with |d_vw| * |d_uv| * max|d_u.| >= c.
 //
-// GPU mapping (persistent grid, two phases per work-group):
-//   * long source rows (len > CAP): one work-group per item (u, 2048-entry chunk). The
-//     chunk of N+(u) is staged in a work-group LDS open-addressing table and the four
-//     waves split the target rows N+(v) round-robin;
+// GPU mapping (persistent grid, two phases per work-group, atomic work queues):
+//   * long source rows (len > CAP = 128): one work-group per item (u, CAPH = 1024-entry
+//     chunk). The chunk of N+(u) is staged in a work-group LDS table and the four waves
+//     split the target rows N+(v) round-robin;
 //   * other source rows: one wave per item, the row staged in the wave's own table.
-//   A target row N+(v) is streamed coalesced with v, its start and length broadcast in
-//   scalar registers; each lane loads up to four ids ahead (64 apart) before probing
-//   them, so every wave keeps several loads in flight. Only hits read d values. The
-//   classify, count, histogram, fixed-point, enumeration and statistics epilogues are
-//   selected at compile time.
+//   Tables are open addressing over buckets of four 32-bit keys, read with one 16-byte
+//   LDS load, at load factor 1/8 (wave) or 1/4 (work-group), so almost every probe ends
+//   in its home bucket. A target row N+(v) is streamed coalesced with v, its start and
+//   length broadcast in scalar registers; each lane loads up to four ids ahead (64
+//   apart) before probing them, so every wave keeps several loads in flight. Hits are
+//   classified from the d codes packed above the ids; only the few the codes leave
+//   undecided read d values. The classify, count, histogram, fixed-point, enumeration
+//   and statistics epilogues are selected at compile time.
 #include <algorithm>
 
 #include "walk_common.h"
@@ -29,23 +32,29 @@ namespace {
 #define UTRI_WALK_CAPH 1024
 #endif
 constexpr int CAPH = UTRI_WALK_CAPH;  // source entries per work-group item
-constexpr int HSH = SLOTS * CAPH;     // work-group table slots (buckets of 4)
+#ifndef UTRI_WALK_SLOTS_WG
+#define UTRI_WALK_SLOTS_WG 4
+#endif
+constexpr int SLOTSH = UTRI_WALK_SLOTS_WG;  // work-group table slots per staged entry
+constexpr int HSH = SLOTSH * CAPH;    // work-group table slots (buckets of 4)
 
 #ifndef UTRI_WALK_UNR_MAX
 #define UTRI_WALK_UNR_MAX 4        // loads in flight per lane on long target rows
 #endif
 #ifndef UTRI_WALK_HASH24
-#define UTRI_WALK_HASH24 0         // 1: 24-bit multiplicative hash
+#define UTRI_WALK_HASH24 0         // 1: full-rate 24-bit multiplicative hash; 0: 32-bit
 #endif
 #ifndef UTRI_WALK_DYNAMIC
 #define UTRI_WALK_DYNAMIC 1        // 1: items handed out by atomic work queues; 0: static stride
 #endif
 
-// slot of w in a 2^lg table of the walk
+// bucket of w in a table of 2^lg buckets (lg >= 1)
 __device__ __forceinline__ uint32_t walk_hash(int32_t w, int lg) {
 #if UTRI_WALK_HASH24
-    // __umul24 returns a signed int: shift the unsigned product, never the signed value
-    return (uint32_t)__umul24((uint32_t)w, 0x9E3779u) >> (32 - lg);
+    // the 24-bit multiplier runs at full rate (the 32-bit one at quarter rate); ids above
+    // 2^24 fold their high bits in. __umul24 returns a signed int: shift the unsigned value
+    const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 24);
+    return (uint32_t)__umul24(x, 0x9E3779u) >> (32 - lg);
 #else
     return utri_hash32(w, lg);
 #endif
@@ -62,7 +71,8 @@ union WalkShared {
     WalkLds wave[WPB];
     BlockLds block;
 };
-static_assert(CAPH >= CAP && CAPH <= 65536 && (CAPH & (CAPH - 1)) == 0,
+static_assert(CAPH >= CAP && CAPH <= 65536 && (CAPH & (CAPH - 1)) == 0 &&
+                  (SLOTSH & (SLOTSH - 1)) == 0,
               "work-group chunks hold every long row's chunk; table sizes are powers of two");
 
 // Bounds of the two item lists: light items (one per source row with 2 <= len <= CAP)
@@ -184,7 +194,9 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
 #endif
     constexpr bool kCoded = UTRI_WALK_CODES && (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
                                                 MODE == WALK_ENUM_FILL);
-    const uint32_t* rowp = (const uint32_t*)o_adj + ovs;  // wave-uniform row base
+    // wave-uniform row base; in-row byte offsets are 32-bit (oriented rows under Node
+    // Order are far shorter than 2^30 entries), so loads take the scalar-base form
+    const char* rowb = (const char*)((const uint32_t*)o_adj + ovs);
     const double* rowd = o_d + ovs;
     for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
         // all UNR loads are issued before any probe; lanes past the row end re-load its
@@ -193,7 +205,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;
-            pw[k] = rowp[min(j, lvs - 1)];
+            pw[k] = *(const uint32_t*)(rowb + ((uint32_t)min(j, lvs - 1) << 2));
         }
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
@@ -201,22 +213,23 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             const uint32_t w = pw[k] & wp.idmask;
             bool is_b = false, is_u = false;
             // linear probe over 4-slot buckets until the key or a bucket with an empty
-            // slot (-1, never a packed word; tested first because -1 & idmask can be a
-            // real id). Slots of a bucket fill in order, so its last slot tells.
+            // slot. Empty slots hold 0, whose id part (vertex 0, the lowest rank) is in no
+            // oriented row, so it never matches w. Slots of a bucket fill in order, so its
+            // last slot tells whether the bucket is full.
             uint32_t b = walk_hash((int32_t)w, R.lg);
             int kk, h;
             for (;;) {
                 const int4 kv = *reinterpret_cast<const int4*>(R.key + 4 * b);
-                const bool f0 = kv.x != -1 && ((uint32_t)kv.x & wp.idmask) == w;
-                const bool f1 = kv.y != -1 && ((uint32_t)kv.y & wp.idmask) == w;
-                const bool f2 = kv.z != -1 && ((uint32_t)kv.z & wp.idmask) == w;
-                const bool f3 = kv.w != -1 && ((uint32_t)kv.w & wp.idmask) == w;
+                const bool f0 = ((uint32_t)kv.x & wp.idmask) == w;
+                const bool f1 = ((uint32_t)kv.y & wp.idmask) == w;
+                const bool f2 = ((uint32_t)kv.z & wp.idmask) == w;
+                const bool f3 = ((uint32_t)kv.w & wp.idmask) == w;
                 kk = f0 ? kv.x : f1 ? kv.y : f2 ? kv.z : f3 ? kv.w : -1;
                 h = 4 * (int)b + (f0 ? 0 : f1 ? 1 : f2 ? 2 : 3);
                 // keep the results in registers here: otherwise the compiler carries the
                 // four match flags out of the loop as scalar lane masks
                 asm volatile("" : "+v"(kk), "+v"(h));
-                if (kk != -1 || kv.w == -1) break;
+                if (kk != -1 || kv.w == 0) break;
                 b = (b + 1) & R.mask;
             }
             if (j < lvs && kk != -1) {
@@ -340,22 +353,23 @@ __device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, i
                                             int nthreads, uint32_t idmask) {
     const uint32_t mask = (1u << lg) - 1u;
     for (int j = tid; j < cl; j += nthreads) {
-        // the key is the packed word (id and d code); it is never -1, the empty marker
+        // the key is the packed word (id and d code); its id is at least 1, so it is
+        // never 0, the empty marker (and never -1, the probe's not-found value)
         const int32_t pw = o_adj[base + j];
         uint32_t b = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
         for (;;) {
             int s = 0;
-            while (s < 4 && atomicCAS(&key[4 * b + s], -1, pw) != -1) s++;
+            while (s < 4 && atomicCAS(&key[4 * b + s], 0, pw) != 0) s++;
             if (s < 4) { pos[4 * b + s] = (uint16_t)j; break; }
             b = (b + 1) & mask;
         }
     }
 }
 
-// log2 of the bucket count of a table for cl entries: 4 * 2^lg >= SLOTS * cl, 2^lg >= 2
-__device__ __forceinline__ int table_lg(int cl) {
+// log2 of the bucket count of a table for cl entries: 4 * 2^lg >= slots * cl, 2^lg >= 2
+__device__ __forceinline__ int table_lg(int cl, int slots) {
     int lg = 1;
-    while ((4 << lg) < SLOTS * cl) lg++;
+    while ((4 << lg) < slots * cl) lg++;
     return lg;
 }
 
@@ -368,9 +382,9 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const int lane = utri_lane();
     const int64_t ou = o_off[u];
     const int Lu = len[u];
-    const int lg = table_lg(Lu);
+    const int lg = table_lg(Lu, SLOTS);
     const int nbk = 1 << lg;  // buckets
-    for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) L.key[i] = -1;
+    for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) L.key[i] = 0;
     utri_wave_sync();
     stage_table(o_adj, ou, Lu, L.key, L.pos, lg, lane, UTRI_WAVE, wp.idmask);
     utri_wave_sync();
@@ -421,10 +435,10 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     const int Lu = len[u];
     const int cb = chunk * CAPH;
     const int cl = min(CAPH, Lu - cb);
-    const int lg = table_lg(cl);
+    const int lg = table_lg(cl, SLOTSH);
     const int nbk = 1 << lg;  // buckets
     __syncthreads();  // the previous item's probes are done
-    for (int i = threadIdx.x; i < 4 * nbk; i += TPB) B.key[i] = -1;
+    for (int i = threadIdx.x; i < 4 * nbk; i += TPB) B.key[i] = 0;
     __syncthreads();
     stage_table(o_adj, ou + cb, cl, B.key, B.pos, lg, threadIdx.x, TPB, wp.idmask);
     __syncthreads();

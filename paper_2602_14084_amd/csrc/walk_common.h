@@ -9,13 +9,13 @@ namespace utri_dev {
 constexpr int TPB = 256;
 constexpr int WPB = TPB / UTRI_WAVE;
 #ifndef UTRI_WALK_CAP
-#define UTRI_WALK_CAP 256
+#define UTRI_WALK_CAP 128
 #endif
 #ifndef UTRI_WALK_SLOTS
-#define UTRI_WALK_SLOTS 4
+#define UTRI_WALK_SLOTS 8
 #endif
 constexpr int CAP = UTRI_WALK_CAP;  // longest source row staged by one wave
-constexpr int SLOTS = UTRI_WALK_SLOTS;  // table slots per staged entry (load factor 1/SLOTS)
+constexpr int SLOTS = UTRI_WALK_SLOTS;  // wave-table slots per staged entry (load factor 1/SLOTS)
 constexpr int HS = SLOTS * CAP;     // LDS table slots, in buckets of 4
 // a table for cl <= CAP entries has the least power-of-two bucket count with 4 * buckets
 // >= SLOTS * cl (at least 2 buckets): with powers of two that is at most HS slots
