@@ -202,8 +202,10 @@ __global__ void k_pack_oriented(int32_t* __restrict__ o_adj, const double* __res
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const double d = o_d[i];
-    const uint32_t qmax = (1u << mb) - 2u;
-    uint32_t q = (uint32_t)(fabs(d) * (double)(1u << mb));  // floor: |d| >= q * 2^-mb
+    const uint32_t qmax = (1u << mb) - 1u;
+    // floor (exact: a power-of-two scaling): q <= |d| * 2^mb < q + 1; |d| = 1 maps to
+    // 2^mb - 1, whose bucket [q, q + 1] * 2^-mb still holds it
+    uint32_t q = (uint32_t)(fabs(d) * (double)(1u << mb));
     if (q > qmax) q = qmax;
     const uint32_t sign = d < 0.0 ? 1u : 0u;
     const uint32_t code = (sign << mb) | q;

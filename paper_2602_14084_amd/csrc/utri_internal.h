@@ -118,8 +118,9 @@ struct utri_graph {
     double* o_d = nullptr;
     int32_t* o_eid = nullptr;
     // Oriented-row packing. Ids take the low `idbits` bits; when at least three bits are
-    // left, the high bits hold sign(d) and q = floor(|d| * 2^mb) (at most 2^mb - 2, the top
-    // bucket reaching 1), so |d| lies in [q, q + 1] * 2^-mb (the top bucket in [q * 2^-mb, 1]).
+    // left, the high bits hold sign(d) and q = min(floor(|d| * 2^mb), 2^mb - 1), so |d|
+    // lies in [q, q + 1] * 2^-mb. Ids are at least 1 (vertex 0 has the lowest rank and is
+    // in no oriented row), so a packed word is never 0.
     int idbits = 31;
     int code_mb = 0;             // magnitude bits of the code, 0 = no code
     uint32_t idmask = 0x7FFFFFFFu;

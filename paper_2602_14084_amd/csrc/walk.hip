@@ -133,7 +133,7 @@ struct RowCtx {
 
 // Per-row integer thresholds of the code decision. With A = |d_uv| and code magnitudes
 // qb (of d_uw) and qc (of d_vw), |s| lies in [A * P0, A * P1] * 2^-2mb with P0 = qb * qc and
-// P1 = qb' * qc' (q' = q + 1, or 2^mb for the top bucket). With K = c * 2^2mb / A:
+// P1 = (qb + 1) * (qc + 1). With K = c * 2^2mb / A:
 //   P0 >= khi = floor(K (1 + 2^-40)) + 1   =>  |s| > c  (balanced if s < 0, else unbalanced)
 //   P1 <= klo = floor(K (1 - 2^-40))       =>  |s| < c  (neither)
 // The 2^-40 margins exceed the roundings of K and the 2^-51 gap between the real product
@@ -164,12 +164,9 @@ __device__ __forceinline__ CodeRow code_row(const WalkParams& wp, double duv) {
 __device__ __forceinline__ int code_decide(const WalkParams& wp, const CodeRow& r, uint32_t cu,
                                            uint32_t cv) {
     const uint32_t mmask = (1u << wp.mb) - 1u;
-    const uint32_t qtop = mmask - 1u;
     const uint32_t qb = cu & mmask, qc = cv & mmask;
-    const uint32_t qb1 = qb >= qtop ? mmask + 1u : qb + 1u;
-    const uint32_t qc1 = qc >= qtop ? mmask + 1u : qc + 1u;
-    // operands are below 2^16: the 24-bit multiplier is exact (its result is a signed int)
-    uint32_t p0 = (uint32_t)__umul24(qb, qc), p1 = (uint32_t)__umul24(qb1, qc1);
+    // operands are at most 2^15: the 24-bit multiplier is exact (its result is a signed int)
+    uint32_t p0 = (uint32_t)__umul24(qb, qc), p1 = (uint32_t)__umul24(qb + 1u, qc + 1u);
     // both products in registers first, so the selects below stay selects (the caller
     // evaluates this on every lane; branches would only add exec-mask work)
     asm volatile("" : "+v"(p0), "+v"(p1));
@@ -216,6 +213,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             // slot. Empty slots hold 0, whose id part (vertex 0, the lowest rank) is in no
             // oriented row, so it never matches w. Slots of a bucket fill in order, so its
             // last slot tells whether the bucket is full.
+            // kk: the matching packed key, 0 if none; h: its slot
             uint32_t b = walk_hash((int32_t)w, R.lg);
             int kk, h;
             for (;;) {
@@ -224,15 +222,15 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                 const bool f1 = ((uint32_t)kv.y & wp.idmask) == w;
                 const bool f2 = ((uint32_t)kv.z & wp.idmask) == w;
                 const bool f3 = ((uint32_t)kv.w & wp.idmask) == w;
-                kk = f0 ? kv.x : f1 ? kv.y : f2 ? kv.z : f3 ? kv.w : -1;
+                kk = f0 ? kv.x : f1 ? kv.y : f2 ? kv.z : f3 ? kv.w : 0;
                 h = 4 * (int)b + (f0 ? 0 : f1 ? 1 : f2 ? 2 : 3);
                 // keep the results in registers here: otherwise the compiler carries the
                 // four match flags out of the loop as scalar lane masks
                 asm volatile("" : "+v"(kk), "+v"(h));
-                if (kk != -1 || kv.w == 0) break;
+                if (kk != 0 || kv.w == 0) break;
                 b = (b + 1) & R.mask;
             }
-            if (j < lvs && kk != -1) {
+            if (j < lvs && kk != 0) {
                 const uint32_t hkey = (uint32_t)kk;
                 if (MODE == WALK_STATS) {
                     st.tri++;
@@ -354,7 +352,7 @@ __device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, i
     const uint32_t mask = (1u << lg) - 1u;
     for (int j = tid; j < cl; j += nthreads) {
         // the key is the packed word (id and d code); its id is at least 1, so it is
-        // never 0, the empty marker (and never -1, the probe's not-found value)
+        // never 0, the empty marker and the probe's not-found value
         const int32_t pw = o_adj[base + j];
         uint32_t b = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
         for (;;) {
