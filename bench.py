@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_count_traffic.json")
+# the walk kernel and what fixes its inputs' layout (the row packing is done at ingest)
 WALK_SOURCES = ["paper_2602_14084_amd/csrc/walk.hip", "paper_2602_14084_amd/csrc/walk_common.h",
-                "paper_2602_14084_amd/csrc/utri_internal.h"]
+                "paper_2602_14084_amd/csrc/utri_internal.h", "paper_2602_14084_amd/csrc/ingest.hip"]
 
 
 def log(*a):
