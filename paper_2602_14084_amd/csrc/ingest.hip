@@ -568,7 +568,8 @@ static int load_impl(const int64_t* src, const int64_t* dst, const double* p, in
     UTRI_TRY(dev_alloc(&g->s_eid, 2 * m));
     UTRI_TRY(dev_alloc(&g->s_row, 2 * m));
     UTRI_TRY(dev_alloc(&g->o_off, n + 1));
-    UTRI_TRY(dev_alloc(&g->o_adj, m));
+    UTRI_TRY(dev_alloc(&g->o_adj, m + UTRI_ROW_PAD));
+    UTRI_HIP_TRY(hipMemsetAsync(g->o_adj + m, 0, sizeof(int32_t) * UTRI_ROW_PAD, s));
     UTRI_TRY(dev_alloc(&g->o_d, m));
     UTRI_TRY(dev_alloc(&g->o_eid, m));
     UTRI_TRY(dev_alloc(&g->h_off, n + 1));

@@ -22,6 +22,9 @@
 #include "utri.h"
 
 #define UTRI_WAVE 64
+// readable entries the oriented id array carries past its last row: a row stream loads
+// whole groups of up to 8 strips of 64 without clamping to the row end
+#define UTRI_ROW_PAD 512
 
 // ------------------------------------------------------------------ error plumbing
 

@@ -192,18 +192,18 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
     constexpr bool kCoded = UTRI_WALK_CODES && (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
                                                 MODE == WALK_ENUM_FILL);
     // wave-uniform row base; in-row byte offsets are 32-bit (oriented rows under Node
-    // Order are far shorter than 2^30 entries), so loads take the scalar-base form
+    // Order are far shorter than 2^30 entries), so loads take the scalar-base form with the
+    // strip offsets as immediates. Lanes past the row end read on (the id array is padded
+    // by UTRI_ROW_PAD entries) and their results are dropped.
+    static_assert(UNR * UTRI_WAVE <= UTRI_ROW_PAD, "row streams stay inside the padding");
     const char* rowb = (const char*)((const uint32_t*)o_adj + ovs);
     const double* rowd = o_d + ovs;
     for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
-        // all UNR loads are issued before any probe; lanes past the row end re-load its
-        // last entry (always in bounds) and drop the result below
+        // all UNR loads are issued before any probe
         uint32_t pw[UNR];
+        const char* lb = rowb + (((uint32_t)(j0 + lane)) << 2);
 #pragma unroll
-        for (int k = 0; k < UNR; k++) {
-            const int j = j0 + k * UTRI_WAVE + lane;
-            pw[k] = *(const uint32_t*)(rowb + ((uint32_t)min(j, lvs - 1) << 2));
-        }
+        for (int k = 0; k < UNR; k++) pw[k] = *(const uint32_t*)(lb + k * 4 * UTRI_WAVE);
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;
@@ -256,8 +256,8 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                         }
                     }
                     if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) {
-                        if (dec == 1) st.nb++;
-                        else if (dec == 2) st.nu++;
+                        st.nb += (dec == 1) ? 1u : 0u;
+                        st.nu += (dec == 2) ? 1u : 0u;
                     } else if (MODE == WALK_ENUM_FILL) {
                         is_b = (dec == 1) && (wp.which & UTRI_BAL);
                         is_u = (dec == 2) && (wp.which & UTRI_UNBAL);
