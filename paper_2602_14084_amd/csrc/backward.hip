@@ -4,23 +4,23 @@
 // product form, d = 1 - 2 P+). With dd_e/dp_e = -2, dE/dp_e = sum over the triangles
 // (e, f, g) through e of d_f * d_g.
 //
-// Edge-centric re-walk grouped by owner. Edge (x, y) with x < y in Node Order (so
-// deg x <= deg y) is owned by y: its triangles are the w of N(x) that are also in N(y),
-// found by streaming N(x) (cost deg x = min(deg x, deg y)) and probing a table of N(y).
-// The owner's row is prepared once for many of its edges:
-//   * deg y <= CAPW: an exact LDS hash table of one wave (one item per owner);
-//   * deg y <= CAPB: an exact LDS hash table of one work-group, its waves splitting the
-//     owner's edges;
-//   * hubs: the row does not fit in LDS. Each work-group item (a range of the hub's row
-//     positions) builds a blocked Bloom filter of N(y) in LDS; streamed entries that pass
-//     it (the hits and a few percent of false positives) are confirmed 64 at a time in
-//     the row's global hash table. Hub items are queued per XCD (work-group index mod 8,
-//     the hardware's round-robin placement), so the one or two hubs an XCD works through
-//     at a time keep their tables in its L2.
-// Each product d_xw * d_yw is rounded to FP64 and added exactly in 2^-62 fixed point in
-// lane registers, reduced over the wave once per edge and rounded once: the result does
-// not depend on which lane found which triangle. Every edge has one writer and no
-// atomics touch the result.
+// Every triangle u < v < w (Node Order) is found by two walks over the degree-oriented
+// rows O(.) and hands each of its edges the product of the other two d values:
+//   * pass A, the forward walk's order: O(u) is staged in an LDS table with one
+//     accumulator per entry and O(v) is streamed for every v in O(u). A hit w adds
+//     d_uw * d_vw to the row sum of (u, v), reduced over the wave when the row ends and
+//     added to v's entry, and d_uv * d_vw to w's entry, the edge (u, w);
+//   * pass B, middle vertex first: O(v) is staged likewise and O(u) is streamed for every
+//     in-neighbour u of v (an entry x < v of the symmetric row N(v)). A hit w adds
+//     d_uv * d_uw to w's entry, the edge (v, w).
+// The two passes stream sum_u |O(u)| (|O(u)| + |I(u)|) = sum_e min(deg) entries, the
+// edge-centric cost, and every probe is an LDS bucket read (no hub tables in global
+// memory). An entry's sum has one writer, the wave or work-group that staged the row.
+// Rows longer than one table are cut into chunks and in-neighbour lists into ranges of the
+// symmetric row; each (chunk, range) item writes its own slice of a partial-sum array and
+// a final pass adds the slices of every oriented edge and rounds once. Each product is
+// rounded to FP64, then summed exactly in 2^-62 fixed point (as two 64-bit half sums), so
+// the result does not depend on the order and no atomics touch global memory.
 #include <algorithm>
 
 #include "walk_common.h"
@@ -29,396 +29,415 @@ using namespace utri_dev;
 
 namespace {
 
-#ifndef UTRI_GRAD_CAPW
-#define UTRI_GRAD_CAPW 256
+#ifndef UTRI_GRAD_CAP
+#define UTRI_GRAD_CAP 128       // longest row staged by one wave
 #endif
-#ifndef UTRI_GRAD_CAPB
-#define UTRI_GRAD_CAPB 2048
+#ifndef UTRI_GRAD_SLOTS
+#define UTRI_GRAD_SLOTS 4       // wave-table slots per staged entry
 #endif
-#ifndef UTRI_GRAD_FILTER_WORDS
-#define UTRI_GRAD_FILTER_WORDS 5632
+#ifndef UTRI_GRAD_CAPH
+#define UTRI_GRAD_CAPH 1024     // row chunk staged by one work-group
 #endif
-constexpr int GCAPW = UTRI_GRAD_CAPW;  // longest owner row staged by one wave
-constexpr int GCAPB = UTRI_GRAD_CAPB;  // longest owner row staged by one work-group
-constexpr int GFW = UTRI_GRAD_FILTER_WORDS;  // 32-bit words of a hub row's LDS filter
-#ifndef UTRI_GRAD_HUB_SPAN
-#define UTRI_GRAD_HUB_SPAN 128
+#ifndef UTRI_GRAD_SLOTS_WG
+#define UTRI_GRAD_SLOTS_WG 2    // work-group-table slots per staged entry
 #endif
-// Row positions per hub item (a multiple of 64). Small items put every work-group of an
-// XCD on the same one or two hubs, so their global tables stay in that XCD's L2; the
-// filter is rebuilt per item (a few microseconds against ~100 strips of work).
-constexpr int GSPAN = UTRI_GRAD_HUB_SPAN;
-static_assert(GSPAN % UTRI_WAVE == 0, "hub items cover whole 64-position chunks");
-constexpr int NXCD = 8;                // hub work queues (one per XCD)
-constexpr int GGROUP = 4;              // wave owners taken per queue grab
-constexpr int GQCAP = 2 * UTRI_WAVE;   // filter-passing entries a wave holds back
-static_assert(GCAPW <= GCAPB && GCAPB <= 32768, "LDS row positions are 16-bit");
+#ifndef UTRI_GRAD_SPAN
+#define UTRI_GRAD_SPAN 256      // symmetric-row positions scanned by one pass-B item
+#endif
+constexpr int GCAP = UTRI_GRAD_CAP;
+constexpr int GSL = UTRI_GRAD_SLOTS;
+constexpr int GCAPH = UTRI_GRAD_CAPH;
+constexpr int GSLH = UTRI_GRAD_SLOTS_WG;
+constexpr int GSPAN = UTRI_GRAD_SPAN;
+constexpr int GGROUP = 4;  // wave items taken per queue grab
+static_assert((GCAP & (GCAP - 1)) == 0 && (GCAPH & (GCAPH - 1)) == 0 && GCAP <= GCAPH &&
+                  GCAPH <= 65536 && (GSL & (GSL - 1)) == 0 && (GSLH & (GSLH - 1)) == 0 &&
+                  GCAP * GSL >= 8 && GSPAN % UTRI_WAVE == 0,
+              "table sizes are powers of two; item ranges are whole strips");
+
+// An oriented row has at most sqrt(2m) < 2^16 entries (its entries have at least its own
+// degree), so a row has at most 64 chunks; a symmetric row has fewer than 2^23 ranges.
+// Pass-B work-group items pack (vertex, range, chunk) as 32 + 24 + 8 bits.
+constexpr int RANGE_SHIFT = 32, CHUNK_SHIFT = 56;
 
 struct GWaveLds {
-    int32_t key[2 * GCAPW];
-    uint16_t pos[2 * GCAPW];
+    alignas(16) int32_t key[GCAP * GSL];
+    uint16_t pos[GCAP * GSL];
+    unsigned long long lo[GCAP];  // per entry: sum of the low 32 bits of its terms
+    unsigned long long hi[GCAP];  // per entry: sum of the terms shifted right by 32
 };
 struct GBlockLds {
-    int32_t key[2 * GCAPB];
-    uint16_t pos[2 * GCAPB];
-};
-// Entries of a streamed row that passed a hub filter, waiting to be confirmed 64 at a
-// time in the hub's global table (so the global probes run on full waves).
-struct GQueue {
-    int32_t w[GQCAP];  // vertex id
-    int32_t j[GQCAP];  // position in the streamed row
-};
-struct GHubLds {
-    uint32_t filt[GFW];
-    GQueue q[WPB];
+    alignas(16) int32_t key[GCAPH * GSLH];
+    uint16_t pos[GCAPH * GSLH];
+    unsigned long long lo[GCAPH];
+    unsigned long long hi[GCAPH];
 };
 union GShared {
     GWaveLds wave[WPB];
     GBlockLds block;
-    GHubLds hub;
 };
 
 struct GradParams {
+    const int64_t* o_off;
+    const int32_t* o_adj;      // packed words: id in the low bits
+    const double* o_d;
+    const int32_t* o_eid;
     const int64_t* s_off;
     const int32_t* s_adj;
     const double* s_d;
-    const int32_t* s_eid;
-    const int64_t* h_off;      // symmetric-row hash tables (slot = id << 32 | position)
-    const uint64_t* h_slot;
+    uint32_t idmask;
+    const int64_t* pa_off;     // [n+1] pass-A slices: chunks x |O(u)| entries per source u
+    const int64_t* pb_off;     // [n+1] pass-B slices: ranges x |O(v)| entries per middle v
+    ulonglong2* pa;            // (low-half sum, high-half sum) per entry and slice
+    ulonglong2* pb;
+    const int64_t* items;      // A-wave | A-block | B-wave | B-block item lists
+    int64_t n_aw, n_ab, n_bw, n_bb;
+    unsigned long long* qctr;  // four work-queue counters, zeroed per launch
     double* grad;
-    const int64_t* items;      // [0, n) wave owners, [n, 2n) work-group owners, [2n, ...) hub items
-    const int64_t* cnt;        // device: # wave owners, # work-group owners, # hub items
-    unsigned long long* qctr;  // [0] work-group owners, [1, 9) hub queues, [9] wave owners
     int64_t n;
 };
 
-struct LdsTab {
+// The staged row (or chunk) of one item.
+struct GTab {
     const int32_t* key;
     const uint16_t* pos;
     int lg;
     uint32_t mask;
-};
-struct HubTab {
-    const uint64_t* slot;  // the row's global table, ~0 = empty slot
-    int lg;
-    uint32_t mask;
-    const uint32_t* filt;  // LDS blocked Bloom filter of the row
-    GQueue* q;             // the wave's queue of filter-passing entries
+    unsigned long long* lo;
+    unsigned long long* hi;
+    int64_t src;  // position of the staged entries in o_adj / o_d
 };
 
-// Filter word and the two bits of id w (both bits in one word: one LDS read per test).
-struct FilterKey {
-    uint32_t word, bits;
-};
-__device__ __forceinline__ FilterKey filter_key(int32_t w) {
-    const uint32_t x = (uint32_t)w * 0x9E3779B1u;
-    const uint32_t y = (x ^ (x >> 15)) * 0x2C1B3C6Du;
-    return {__umulhi(x, (uint32_t)GFW), (1u << (y >> 27)) | (1u << ((y >> 22) & 31u))};
+__device__ __forceinline__ int64_t fix_prod(double a, double b) {
+    return utri_fix62(__dmul_rn(a, b));
 }
 
-__device__ __forceinline__ void acc_term(uint64_t& slo, int64_t& shi, double a, double b) {
-    const int64_t t = utri_fix62(__dmul_rn(a, b));
-    slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
-    shi += t >> 32;
-}
-
-// Reduce the lanes' fixed-point partial sums of one edge and store the rounded value.
-__device__ __forceinline__ void grad_store(double* __restrict__ grad, int32_t eid, uint64_t slo,
-                                           int64_t shi) {
-    const uint64_t l = utri_wave_sum_u64(slo);
-    const int64_t h = (int64_t)utri_wave_sum_u64((uint64_t)shi);
-    if (utri_lane() == 0) {
-        // value = h * 2^32 + l as a 128-bit two's complement number
-        uint64_t lo = (uint64_t)h << 32;
-        uint64_t hi = (uint64_t)(h >> 32);
-        const uint64_t s2 = lo + l;
-        hi += (s2 < lo) ? 1ull : 0ull;
-        lo = s2;
-        grad[eid] = utri_i128_to_double((int64_t)hi, lo) * 0x1p-62;
-    }
-}
-
-// Stream N(x) = s_adj[xoff, xoff + lx) and add d_xw * d_yw for every w found in the
-// owner's LDS table. Lanes past the row end re-load its last entry and drop the result;
-// all UNR loads are issued before any probe.
-template <int UNR>
-__device__ __forceinline__ void grad_row(const GradParams& P, const LdsTab& LT,
-                                         const double* __restrict__ yd, int64_t xoff, int lx,
-                                         uint64_t& slo, int64_t& shi) {
+// Stream the oriented row [ovs, ovs + lvs) and handle every entry found in the table.
+// Pass A (row O(v), dpair = d_uv): adds d_uw * d_vw to the lane's row sum and
+// d_uv * d_vw to the hit entry. Pass B (row O(u), dpair = d_uv): adds d_uv * d_uw to the
+// hit entry. Lanes past the row end read on (the id array is padded) and are dropped.
+template <bool PASS_A, int UNR>
+__device__ __forceinline__ void g_stream(const GradParams& P, const GTab& T, int64_t ovs, int lvs,
+                                         double dpair, uint64_t& slo, int64_t& shi) {
+    static_assert(UNR * UTRI_WAVE <= UTRI_ROW_PAD, "row streams stay inside the padding");
     const int lane = utri_lane();
-    const int32_t* rowp = P.s_adj + xoff;
-    const double* rowd = P.s_d + xoff;
-    for (int j0 = 0; j0 < lx; j0 += UNR * UTRI_WAVE) {
-        int32_t w[UNR];
+    const char* rowb = (const char*)((const uint32_t*)P.o_adj + ovs);
+    const double* rowd = P.o_d + ovs;
+    for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
+        uint32_t pw[UNR];
+        const char* lb = rowb + (((uint32_t)(j0 + lane)) << 2);
 #pragma unroll
-        for (int k = 0; k < UNR; k++) w[k] = rowp[min(j0 + k * UTRI_WAVE + lane, lx - 1)];
+        for (int k = 0; k < UNR; k++) pw[k] = *(const uint32_t*)(lb + k * 4 * UTRI_WAVE);
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;
-            uint32_t h = utri_hash32(w[k], LT.lg);
-            int kk = LT.key[h];
-            while (kk != -1 && kk != w[k]) {
-                h = (h + 1) & LT.mask;
-                kk = LT.key[h];
-            }
-            if (j < lx && kk != -1) acc_term(slo, shi, rowd[j], yd[LT.pos[h]]);
-        }
-    }
-}
-
-// Confirm queue entries [base, base + cnt) (cnt <= 64, one per lane) in the hub's global
-// table and add the products of the hits.
-__device__ __forceinline__ void hub_confirm(const HubTab& HT, const double* __restrict__ rowd,
-                                            const double* __restrict__ yd, int base, int cnt,
-                                            uint64_t& slo, int64_t& shi) {
-    const int lane = utri_lane();
-    if (lane < cnt) {
-        const int32_t w = HT.q->w[base + lane];
-        const int j = HT.q->j[base + lane];
-        uint32_t h = utri_hash32(w, HT.lg);
-        uint64_t sl = HT.slot[h];
-        while (sl != ~0ull && (int32_t)(sl >> 32) != w) {
-            h = (h + 1) & HT.mask;
-            sl = HT.slot[h];
-        }
-        if (sl != ~0ull) acc_term(slo, shi, rowd[j], yd[(uint32_t)(sl & 0xFFFFFFFFull)]);
-    }
-    utri_wave_sync();  // the entries are read before later ones overwrite them
-}
-
-// Hub variant: entries that pass the LDS filter are appended to the wave's queue, and
-// every full 64 of them are confirmed together; the rest at the end of the row.
-template <int UNR>
-__device__ __forceinline__ void grad_row_hub(const GradParams& P, const HubTab& HT,
-                                             const double* __restrict__ yd, int64_t xoff, int lx,
-                                             uint64_t& slo, int64_t& shi) {
-    const int lane = utri_lane();
-    const int32_t* rowp = P.s_adj + xoff;
-    const double* rowd = P.s_d + xoff;
-    const uint64_t lt = __lanemask_lt();
-    int qn = 0;  // queued entries (wave-uniform, < 64 between strips)
-    for (int j0 = 0; j0 < lx; j0 += UNR * UTRI_WAVE) {
-        int32_t w[UNR];
-#pragma unroll
-        for (int k = 0; k < UNR; k++) w[k] = rowp[min(j0 + k * UTRI_WAVE + lane, lx - 1)];
-#pragma unroll
-        for (int k = 0; k < UNR; k++) {
-            const int j = j0 + k * UTRI_WAVE + lane;
-            const FilterKey fk = filter_key(w[k]);
-            const bool pass = (j < lx) && (HT.filt[fk.word] & fk.bits) == fk.bits;
-            const uint64_t M = __ballot(pass);
-            if (pass) {
-                const int r = qn + __popcll(M & lt);
-                HT.q->w[r] = w[k];
-                HT.q->j[r] = j;
-            }
-            qn += __popcll(M);
-            utri_wave_sync();
-            if (qn >= UTRI_WAVE) {
-                qn -= UTRI_WAVE;
-                hub_confirm(HT, rowd, yd, qn, UTRI_WAVE, slo, shi);
+            int h;
+            const int kk = bucket_find(T.key, T.lg, T.mask, pw[k] & P.idmask, P.idmask, h);
+            if (j < lvs && kk != 0) {
+                const int hit = T.pos[h];
+                const double dx = rowd[j];
+                if (PASS_A) {
+                    const int64_t t1 = fix_prod(P.o_d[T.src + hit], dx);
+                    slo += (uint64_t)(uint32_t)(t1 & 0xFFFFFFFFll);
+                    shi += t1 >> 32;
+                }
+                const int64_t t2 = fix_prod(dpair, dx);
+                atomicAdd(&T.lo[hit], (unsigned long long)(uint32_t)(t2 & 0xFFFFFFFFll));
+                atomicAdd(&T.hi[hit], (unsigned long long)(t2 >> 32));
             }
         }
     }
-    if (qn > 0) hub_confirm(HT, rowd, yd, 0, qn, slo, shi);
 }
 
-template <bool HUB>
-__device__ __forceinline__ void grad_row_any(const GradParams& P, const LdsTab& LT,
-                                             const HubTab& HT, const double* __restrict__ yd,
-                                             int64_t xoff, int lx, uint64_t& slo, int64_t& shi) {
-    if (HUB) {
-        if (lx > 2 * UTRI_WAVE) grad_row_hub<4>(P, HT, yd, xoff, lx, slo, shi);
-        else if (lx > UTRI_WAVE) grad_row_hub<2>(P, HT, yd, xoff, lx, slo, shi);
-        else grad_row_hub<1>(P, HT, yd, xoff, lx, slo, shi);
-    } else {
-        if (lx > 2 * UTRI_WAVE) grad_row<4>(P, LT, yd, xoff, lx, slo, shi);
-        else if (lx > UTRI_WAVE) grad_row<2>(P, LT, yd, xoff, lx, slo, shi);
-        else grad_row<1>(P, LT, yd, xoff, lx, slo, shi);
-    }
+template <bool PASS_A>
+__device__ __forceinline__ void g_stream_any(const GradParams& P, const GTab& T, int64_t ovs,
+                                             int lvs, double dpair, uint64_t& slo, int64_t& shi) {
+    if (lvs > 2 * UTRI_WAVE) g_stream<PASS_A, 4>(P, T, ovs, lvs, dpair, slo, shi);
+    else if (lvs > UTRI_WAVE) g_stream<PASS_A, 2>(P, T, ovs, lvs, dpair, slo, shi);
+    else if (lvs > 0) g_stream<PASS_A, 1>(P, T, ovs, lvs, dpair, slo, shi);
 }
 
-// Positions [p0, p0 + 64) of the owner row N(y): every x < y there is an owned edge.
-// The wave takes the owned edges whose rank in the chunk is `part` mod `nparts`.
-template <bool HUB>
-__device__ __forceinline__ void owner_chunk(const GradParams& P, int32_t y, int64_t yoff, int D,
-                                            int p0, const LdsTab& LT, const HubTab& HT, int part,
-                                            int nparts) {
-    const int p = p0 + utri_lane();
-    int32_t x = 0, eid = 0;
-    int64_t xoff = 0;
-    int lx = 0;
-    bool owned = false;
-    if (p < D) {
-        x = P.s_adj[yoff + p];
-        owned = x < y;
-    }
-    if (owned) {
-        xoff = P.s_off[x];
-        lx = (int)(P.s_off[x + 1] - xoff);
-        eid = P.s_eid[yoff + p];
-    }
-    uint64_t mask = __ballot(owned);
-    const double* yd = P.s_d + yoff;
-    for (int r = 0; mask; r++) {
-        const int si = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        if (r % nparts != part) continue;
-        uint64_t slo = 0;
-        int64_t shi = 0;
-        grad_row_any<HUB>(P, LT, HT, yd, bcast_i64(xoff, si), bcast_i32(lx, si), slo, shi);
-        grad_store(P.grad, bcast_i32(eid, si), slo, shi);
-    }
+// Clear the table and the accumulators of a chunk of cl entries staged at o_adj[src].
+__device__ __forceinline__ GTab g_clear(int64_t src, int cl, int32_t* key, uint16_t* pos,
+                                        unsigned long long* lo, unsigned long long* hi, int slots,
+                                        int tid, int nthreads) {
+    const int lg = table_lg(cl, slots);
+    const int nbk = 1 << lg;
+    for (int i = tid; i < 4 * nbk; i += nthreads) key[i] = 0;
+    for (int i = tid; i < cl; i += nthreads) { lo[i] = 0; hi[i] = 0; }
+    return GTab{key, pos, lg, (uint32_t)(nbk - 1), lo, hi, src};
 }
 
-__device__ __forceinline__ int grad_table_lg(int cl) {
-    int lg = 1;
-    while ((1 << lg) < 2 * cl) lg++;
-    return lg;
-}
-
-// Insert row positions [0, D) of `row` into a 2^lg-slot LDS table; `tid` / `nthreads`
-// are the caller's lanes (one wave or one work-group).
-__device__ __forceinline__ void grad_stage(const int32_t* __restrict__ row, int D, int32_t* key,
-                                           uint16_t* pos, int lg, int tid, int nthreads) {
-    const uint32_t mask = (1u << lg) - 1u;
-    for (int j = tid; j < D; j += nthreads) {
-        const int32_t w = row[j];
-        uint32_t h = utri_hash32(w, lg);
-        for (;;) {
-            const int old = atomicCAS(&key[h], -1, w);
-            if (old == -1) { pos[h] = (uint16_t)j; break; }
-            h = (h + 1) & mask;
-        }
-    }
-}
-
-__device__ void grad_wave_owner(const GradParams& P, int32_t y, GWaveLds& L) {
+// Pass A over a chunk [cb, cb + cl) of O(u): the rows v = O(u)[i] with (i mod 64) % nparts
+// == part are this wave's. A row sum whose entry is in the chunk goes to its accumulator;
+// otherwise it is the item's own slice entry and is stored directly (also when zero).
+__device__ __forceinline__ void g_pass_a_rows(const GradParams& P, const GTab& T, int64_t ou, int L,
+                                              int cb, int cl, ulonglong2* slice, int part,
+                                              int nparts) {
     const int lane = utri_lane();
-    const int64_t yoff = P.s_off[y];
-    const int D = (int)(P.s_off[y + 1] - yoff);
-    const int lg = grad_table_lg(D);
-    const int size = 1 << lg;
-    for (int i = lane; i < size; i += UTRI_WAVE) L.key[i] = -1;
-    utri_wave_sync();
-    grad_stage(P.s_adj + yoff, D, L.key, L.pos, lg, lane, UTRI_WAVE);
-    utri_wave_sync();
-    const LdsTab T{L.key, L.pos, lg, (uint32_t)(size - 1)};
-    for (int p0 = 0; p0 < D; p0 += UTRI_WAVE) owner_chunk<false>(P, y, yoff, D, p0, T, HubTab{}, 0, 1);
-    utri_wave_sync();  // probes done before the next owner clears the table
-}
-
-__device__ void grad_block_owner(const GradParams& P, int32_t y, GBlockLds& B) {
-    const int wib = threadIdx.x / UTRI_WAVE;
-    const int64_t yoff = P.s_off[y];
-    const int D = (int)(P.s_off[y + 1] - yoff);
-    const int lg = grad_table_lg(D);
-    const int size = 1 << lg;
-    __syncthreads();  // the previous owner's probes are done
-    for (int i = threadIdx.x; i < size; i += TPB) B.key[i] = -1;
-    __syncthreads();
-    grad_stage(P.s_adj + yoff, D, B.key, B.pos, lg, threadIdx.x, TPB);
-    __syncthreads();
-    const LdsTab T{B.key, B.pos, lg, (uint32_t)(size - 1)};
-    for (int p0 = 0; p0 < D; p0 += UTRI_WAVE)
-        owner_chunk<false>(P, y, yoff, D, p0, T, HubTab{}, wib, WPB);
-}
-
-// Work-group item of a hub row: positions [chunk * GSPAN, chunk * GSPAN + GSPAN) of N(y).
-// The filter of N(y) is rebuilt only when the work-group moves to another hub.
-__device__ void grad_hub_item(const GradParams& P, int64_t item, GHubLds& HL, int32_t& cur) {
-    const int wib = threadIdx.x / UTRI_WAVE;
-    const int32_t y = (int32_t)(item & 0xFFFFFFFF);
-    const int chunk = (int)(item >> 32);
-    const int64_t yoff = P.s_off[y];
-    const int D = (int)(P.s_off[y + 1] - yoff);
-    if (y != cur) {
-        __syncthreads();  // the previous hub's probes are done
-        for (int i = threadIdx.x; i < GFW; i += TPB) HL.filt[i] = 0u;
-        __syncthreads();
-        for (int j = threadIdx.x; j < D; j += TPB) {
-            const FilterKey fk = filter_key(P.s_adj[yoff + j]);
-            atomicOr(&HL.filt[fk.word], fk.bits);
+    for (int i0 = 0; i0 < L; i0 += UTRI_WAVE) {
+        const int i = i0 + lane;
+        int64_t ov = 0;
+        int lv = 0;
+        double duv = 0.0;
+        if (i < L) {
+            const int32_t v = (int32_t)((uint32_t)P.o_adj[ou + i] & P.idmask);
+            duv = P.o_d[ou + i];
+            ov = P.o_off[v];
+            lv = (int)(P.o_off[v + 1] - ov);
         }
-        __syncthreads();
-        cur = y;
+        const int nv = min(UTRI_WAVE, L - i0);
+        for (int si = part; si < nv; si += nparts) {
+            uint64_t slo = 0;
+            int64_t shi = 0;
+            g_stream_any<true>(P, T, bcast_i64(ov, si), bcast_i32(lv, si), bcast_f64(duv, si), slo,
+                               shi);
+            const uint64_t l = utri_wave_sum_u64(slo);
+            const uint64_t h = utri_wave_sum_u64((uint64_t)shi);
+            if (lane == 0) {
+                const int iv = i0 + si;
+                if (iv >= cb && iv < cb + cl) {
+                    if (l | h) {
+                        atomicAdd(&T.lo[iv - cb], (unsigned long long)l);
+                        atomicAdd(&T.hi[iv - cb], (unsigned long long)h);
+                    }
+                } else {
+                    slice[iv] = make_ulonglong2(l, h);
+                }
+            }
+        }
     }
-    const int64_t hoff = P.h_off[y];
-    const int64_t size = P.h_off[y + 1] - hoff;  // a power of two
-    const int lg = 63 - __builtin_clzll((unsigned long long)size);
-    const HubTab T{P.h_slot + hoff, lg, (uint32_t)(size - 1), HL.filt, &HL.q[wib]};
-    const int pb = chunk * GSPAN;
+}
+
+// Pass B over range `range` of the symmetric row N(v): the in-neighbours u < v found there
+// whose rank in their 64-position group is part mod nparts are this wave's.
+__device__ __forceinline__ void g_pass_b_rows(const GradParams& P, const GTab& T, int32_t v, int range,
+                                              int part, int nparts) {
+    const int64_t sv = P.s_off[v];
+    const int D = (int)(P.s_off[v + 1] - sv);
+    const int pb = range * GSPAN;
     const int pe = min(D, pb + GSPAN);
-    for (int p0 = pb; p0 < pe; p0 += UTRI_WAVE)
-        owner_chunk<true>(P, y, yoff, pe, p0, LdsTab{}, T, wib, WPB);
+    for (int g0 = pb; g0 < pe; g0 += UTRI_WAVE) {
+        const int p = g0 + utri_lane();
+        int32_t x = 0;
+        bool in = false;
+        if (p < pe) {
+            x = P.s_adj[sv + p];
+            in = x < v;
+        }
+        int64_t ou = 0;
+        int lu = 0;
+        double duv = 0.0;
+        if (in) {
+            ou = P.o_off[x];
+            lu = (int)(P.o_off[x + 1] - ou);
+            duv = P.s_d[sv + p];
+        }
+        uint64_t mask = __ballot(in);
+        for (int r = 0; mask; r++) {
+            const int si = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            if (r % nparts != part) continue;
+            uint64_t slo = 0;
+            int64_t shi = 0;
+            g_stream_any<false>(P, T, bcast_i64(ou, si), bcast_i32(lu, si), bcast_f64(duv, si), slo,
+                                shi);
+        }
+    }
 }
 
-// Persistent grid, three phases per work-group, each fed by atomic work queues:
-// work-group owners (longest rows first), hub items (own XCD's queue, then the others'),
-// wave owners (longest rows first, GGROUP per grab).
-__global__ void __launch_bounds__(TPB) k_grad(GradParams P) {
+__device__ void g_item_a_block(const GradParams& P, int64_t item, GBlockLds& B) {
+    const int wib = threadIdx.x / UTRI_WAVE;
+    const int32_t u = (int32_t)(item & 0xFFFFFFFF);
+    const int chunk = (int)(item >> 32);
+    const int64_t ou = P.o_off[u];
+    const int L = (int)(P.o_off[u + 1] - ou);
+    const int cb = chunk * GCAPH;
+    const int cl = min(GCAPH, L - cb);
+    __syncthreads();  // the previous item is flushed
+    const GTab T = g_clear(ou + cb, cl, B.key, B.pos, B.lo, B.hi, GSLH, threadIdx.x, TPB);
+    __syncthreads();
+    stage_table(P.o_adj, ou + cb, cl, B.key, B.pos, T.lg, threadIdx.x, TPB, P.idmask);
+    __syncthreads();
+    ulonglong2* slice = P.pa + P.pa_off[u] + (int64_t)chunk * L;
+    g_pass_a_rows(P, T, ou, L, cb, cl, slice, wib, WPB);
+    __syncthreads();
+    for (int q = threadIdx.x; q < cl; q += TPB) slice[cb + q] = make_ulonglong2(B.lo[q], B.hi[q]);
+}
+
+__device__ void g_item_b_block(const GradParams& P, int64_t item, GBlockLds& B) {
+    const int wib = threadIdx.x / UTRI_WAVE;
+    const int32_t v = (int32_t)(item & 0xFFFFFFFF);
+    const int range = (int)((item >> RANGE_SHIFT) & 0xFFFFFF);
+    const int chunk = (int)((uint64_t)item >> CHUNK_SHIFT);
+    const int64_t ov = P.o_off[v];
+    const int L = (int)(P.o_off[v + 1] - ov);
+    const int cb = chunk * GCAPH;
+    const int cl = min(GCAPH, L - cb);
+    __syncthreads();  // the previous item is flushed
+    const GTab T = g_clear(ov + cb, cl, B.key, B.pos, B.lo, B.hi, GSLH, threadIdx.x, TPB);
+    __syncthreads();
+    stage_table(P.o_adj, ov + cb, cl, B.key, B.pos, T.lg, threadIdx.x, TPB, P.idmask);
+    __syncthreads();
+    g_pass_b_rows(P, T, v, range, wib, WPB);
+    __syncthreads();
+    ulonglong2* slice = P.pb + P.pb_off[v] + (int64_t)range * L;
+    for (int q = threadIdx.x; q < cl; q += TPB) slice[cb + q] = make_ulonglong2(B.lo[q], B.hi[q]);
+}
+
+__device__ void g_item_a_wave(const GradParams& P, int32_t u, GWaveLds& W) {
+    const int lane = utri_lane();
+    const int64_t ou = P.o_off[u];
+    const int L = (int)(P.o_off[u + 1] - ou);
+    const GTab T = g_clear(ou, L, W.key, W.pos, W.lo, W.hi, GSL, lane, UTRI_WAVE);
+    utri_wave_sync();
+    stage_table(P.o_adj, ou, L, W.key, W.pos, T.lg, lane, UTRI_WAVE, P.idmask);
+    utri_wave_sync();
+    ulonglong2* slice = P.pa + P.pa_off[u];
+    g_pass_a_rows(P, T, ou, L, 0, L, slice, 0, 1);
+    utri_wave_sync();
+    for (int q = lane; q < L; q += UTRI_WAVE) slice[q] = make_ulonglong2(W.lo[q], W.hi[q]);
+    utri_wave_sync();  // read before the next item clears the accumulators
+}
+
+__device__ void g_item_b_wave(const GradParams& P, int64_t item, GWaveLds& W) {
+    const int lane = utri_lane();
+    const int32_t v = (int32_t)(item & 0xFFFFFFFF);
+    const int range = (int)(item >> RANGE_SHIFT);
+    const int64_t ov = P.o_off[v];
+    const int L = (int)(P.o_off[v + 1] - ov);
+    const GTab T = g_clear(ov, L, W.key, W.pos, W.lo, W.hi, GSL, lane, UTRI_WAVE);
+    utri_wave_sync();
+    stage_table(P.o_adj, ov, L, W.key, W.pos, T.lg, lane, UTRI_WAVE, P.idmask);
+    utri_wave_sync();
+    g_pass_b_rows(P, T, v, range, 0, 1);
+    utri_wave_sync();
+    ulonglong2* slice = P.pb + P.pb_off[v] + (int64_t)range * L;
+    for (int q = lane; q < L; q += UTRI_WAVE) slice[q] = make_ulonglong2(W.lo[q], W.hi[q]);
+    utri_wave_sync();  // read before the next item clears the accumulators
+}
+
+// Persistent grid, four atomic work queues, heaviest items (highest ids) first:
+// A work-group items, B work-group items, then A and B wave items, GGROUP per grab.
+__global__ void __launch_bounds__(TPB) k_grad2(GradParams P) {
     __shared__ GShared S;
     __shared__ int64_t s_q;
     const int wib = threadIdx.x / UTRI_WAVE;
     const int lane = utri_lane();
-    const int64_t nw = P.cnt[0], nb = P.cnt[1], nh = P.cnt[2];
+    const int64_t* it_aw = P.items;
+    const int64_t* it_ab = it_aw + P.n_aw;
+    const int64_t* it_bw = it_ab + P.n_ab;
+    const int64_t* it_bb = it_bw + P.n_bw;
     for (;;) {
         if (threadIdx.x == 0) s_q = (int64_t)atomicAdd(&P.qctr[0], 1ull);
         __syncthreads();
         const int64_t q = s_q;
         __syncthreads();
-        if (q >= nb) break;
-        grad_block_owner(P, (int32_t)P.items[P.n + nb - 1 - q], S.block);
+        if (q >= P.n_ab) break;
+        g_item_a_block(P, it_ab[P.n_ab - 1 - q], S.block);
     }
-    const int xcd = (int)(blockIdx.x % NXCD);
-    int32_t cur = -1;  // hub whose filter is in LDS (the union was just used by tables)
-    for (int qq = 0; qq < NXCD; qq++) {
-        const int q = (xcd + qq) % NXCD;
-        const int64_t a = nh * q / NXCD, b = nh * (q + 1) / NXCD;
-        for (;;) {
-            if (threadIdx.x == 0) s_q = (int64_t)atomicAdd(&P.qctr[1 + q], 1ull);
-            __syncthreads();
-            const int64_t t = s_q;
-            __syncthreads();
-            if (a + t >= b) break;
-            grad_hub_item(P, P.items[2 * P.n + (nh - 1 - (a + t))], S.hub, cur);  // largest first
-        }
+    for (;;) {
+        if (threadIdx.x == 0) s_q = (int64_t)atomicAdd(&P.qctr[1], 1ull);
+        __syncthreads();
+        const int64_t q = s_q;
+        __syncthreads();
+        if (q >= P.n_bb) break;
+        g_item_b_block(P, it_bb[P.n_bb - 1 - q], S.block);
     }
-    __syncthreads();  // the filter is no longer read; the wave tables reuse its memory
+    __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
     for (;;) {
         int64_t base = 0;
-        if (lane == 0) base = (int64_t)atomicAdd(&P.qctr[1 + NXCD], (unsigned long long)GGROUP);
+        if (lane == 0) base = (int64_t)atomicAdd(&P.qctr[2], (unsigned long long)GGROUP);
         base = bcast_i64(base, 0);
-        if (base >= nw) break;
-        const int64_t end = base + GGROUP < nw ? base + GGROUP : nw;
+        if (base >= P.n_aw) break;
+        const int64_t end = base + GGROUP < P.n_aw ? base + GGROUP : P.n_aw;
         for (int64_t q = base; q < end; q++)
-            grad_wave_owner(P, (int32_t)P.items[nw - 1 - q], S.wave[wib]);
+            g_item_a_wave(P, (int32_t)it_aw[P.n_aw - 1 - q], S.wave[wib]);
+    }
+    for (;;) {
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd(&P.qctr[3], (unsigned long long)GGROUP);
+        base = bcast_i64(base, 0);
+        if (base >= P.n_bw) break;
+        const int64_t end = base + GGROUP < P.n_bw ? base + GGROUP : P.n_bw;
+        for (int64_t q = base; q < end; q++) g_item_b_wave(P, it_bw[P.n_bw - 1 - q], S.wave[wib]);
     }
 }
 
-// Owner class of every vertex: wave (1 <= deg <= CAPW), work-group (deg <= CAPB), or
-// hub with ceil(deg / GSPAN) items.
-__global__ void k_grad_rows(const int64_t* __restrict__ s_off, int64_t n, int32_t* __restrict__ wcnt,
-                            int32_t* __restrict__ bcnt, int32_t* __restrict__ hcnt) {
-    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= n) return;
-    const int64_t D = s_off[y + 1] - s_off[y];
-    wcnt[y] = (D >= 1 && D <= GCAPW) ? 1 : 0;
-    bcnt[y] = (D > GCAPW && D <= GCAPB) ? 1 : 0;
-    hcnt[y] = D > GCAPB ? (int32_t)((D + GSPAN - 1) / GSPAN) : 0;
+// Per vertex x (L = |O(x)|, D = deg x): pass-A items (one wave item for 2 <= L <= CAP,
+// else ceil(L / CAPH) work-group chunks), pass-B items (ceil(D / SPAN) ranges when x has
+// an out- and an in-neighbour, times the chunks for L > CAP) and the slice sizes.
+__global__ void k_g_counts(const int64_t* __restrict__ o_off, const int64_t* __restrict__ s_off,
+                           int64_t n, int32_t* __restrict__ c_aw, int32_t* __restrict__ c_ab,
+                           int32_t* __restrict__ c_bw, int32_t* __restrict__ c_bb,
+                           int64_t* __restrict__ sz_a, int64_t* __restrict__ sz_b) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t L = o_off[x + 1] - o_off[x];
+    const int64_t D = s_off[x + 1] - s_off[x];
+    const int64_t nch = L > GCAP ? (L + GCAPH - 1) / GCAPH : 1;
+    const int64_t nr = (L >= 1 && D > L) ? (D + GSPAN - 1) / GSPAN : 0;
+    c_aw[x] = (L >= 2 && L <= GCAP) ? 1 : 0;
+    c_ab[x] = L > GCAP ? (int32_t)nch : 0;
+    c_bw[x] = L <= GCAP ? (int32_t)nr : 0;
+    c_bb[x] = L > GCAP ? (int32_t)(nr * nch) : 0;
+    sz_a[x] = L >= 2 ? nch * L : 0;
+    sz_b[x] = nr * L;
 }
 
-__global__ void k_grad_items(const int32_t* __restrict__ wcnt, const int32_t* __restrict__ bcnt,
-                             const int32_t* __restrict__ hcnt, const int64_t* __restrict__ woff,
-                             const int64_t* __restrict__ boff, const int64_t* __restrict__ hoff,
-                             int64_t n, int64_t* __restrict__ items) {
-    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= n) return;
-    if (wcnt[y]) items[woff[y]] = y;
-    if (bcnt[y]) items[n + boff[y]] = y;
-    const int c = hcnt[y];
-    const int64_t o = 2 * n + hoff[y];
-    for (int k = 0; k < c; k++) items[o + k] = ((int64_t)k << 32) | y;
+__global__ void k_g_items(const int64_t* __restrict__ o_off, const int32_t* __restrict__ c_aw,
+                          const int32_t* __restrict__ c_ab, const int32_t* __restrict__ c_bw,
+                          const int32_t* __restrict__ c_bb, const int64_t* __restrict__ f_aw,
+                          const int64_t* __restrict__ f_ab, const int64_t* __restrict__ f_bw,
+                          const int64_t* __restrict__ f_bb, int64_t n, int64_t b_ab,
+                          int64_t b_bw, int64_t b_bb, int64_t* __restrict__ items) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    if (c_aw[x]) items[f_aw[x]] = x;
+    for (int c = 0; c < c_ab[x]; c++) items[b_ab + f_ab[x] + c] = x | ((int64_t)c << 32);
+    for (int r = 0; r < c_bw[x]; r++) items[b_bw + f_bw[x] + r] = x | ((int64_t)r << RANGE_SHIFT);
+    if (c_bb[x]) {
+        const int64_t L = o_off[x + 1] - o_off[x];
+        const int nch = (int)((L + GCAPH - 1) / GCAPH);
+        const int nr = c_bb[x] / nch;
+        int64_t o = b_bb + f_bb[x];
+        for (int r = 0; r < nr; r++)
+            for (int c = 0; c < nch; c++)
+                items[o++] = x | ((int64_t)r << RANGE_SHIFT) | ((int64_t)c << CHUNK_SHIFT);
+    }
+}
+
+// One wave per vertex x: add the pass-A and pass-B slices of every entry of O(x) and
+// store the rounded value at the entry's edge id.
+__global__ void __launch_bounds__(TPB) k_g_final(GradParams P) {
+    const int64_t x = (int64_t)blockIdx.x * WPB + threadIdx.x / UTRI_WAVE;
+    if (x >= P.n) return;
+    const int64_t ox = P.o_off[x];
+    const int L = (int)(P.o_off[x + 1] - ox);
+    if (L == 0) return;
+    const int64_t a0 = P.pa_off[x], b0 = P.pb_off[x];
+    const int na = (int)((P.pa_off[x + 1] - a0) / L);
+    const int nr = (int)((P.pb_off[x + 1] - b0) / L);
+    for (int q = utri_lane(); q < L; q += UTRI_WAVE) {
+        uint64_t l = 0, h = 0;
+        for (int c = 0; c < na; c++) {
+            const ulonglong2 t = P.pa[a0 + (int64_t)c * L + q];
+            l += t.x;
+            h += t.y;
+        }
+        for (int r = 0; r < nr; r++) {
+            const ulonglong2 t = P.pb[b0 + (int64_t)r * L + q];
+            l += t.x;
+            h += t.y;
+        }
+        // value = h * 2^32 + l as a 128-bit two's complement number
+        uint64_t lo = h << 32;
+        uint64_t hi = (uint64_t)((int64_t)h >> 32);
+        const uint64_t s2 = lo + l;
+        hi += (s2 < lo) ? 1ull : 0ull;
+        lo = s2;
+        P.grad[P.o_eid[ox + q]] = utri_i128_to_double((int64_t)hi, lo) * 0x1p-62;
+    }
 }
 
 template <class K>
@@ -430,50 +449,87 @@ int grad_blocks_per_cu(utri_graph* g, K kernel) {
     return nb;
 }
 
+inline unsigned nblocks(int64_t count) { return (unsigned)((count + TPB - 1) / TPB); }
+
 }  // namespace
 
 int utri_grad_launch(utri_graph* g, double* grad, hipStream_t s) {
     if (g->m == 0) return UTRI_OK;
     const int64_t n = g->n;
-    // hub items: ceil(deg / GSPAN) for each of the (< 2m / CAPB) hub rows
-    const int64_t hb = 2 * g->m / GSPAN + 2 * g->m / GCAPB + 2;
-    void *pc, *po, *pi, *pq;
-    UTRI_TRY(utri_scratch(g, SCR_GCNT, sizeof(int32_t) * (size_t)(3 * n), &pc));
-    UTRI_TRY(utri_scratch(g, SCR_GOFF, sizeof(int64_t) * (size_t)(3 * n), &po));
-    UTRI_TRY(utri_scratch(g, SCR_GITEMS, sizeof(int64_t) * (size_t)(2 * n + hb), &pi));
+    void *pc, *po, *pz, *pq;
+    UTRI_TRY(utri_scratch(g, SCR_GCNT, sizeof(int32_t) * (size_t)(4 * n), &pc));
+    UTRI_TRY(utri_scratch(g, SCR_GOFF, sizeof(int64_t) * (size_t)(6 * n + 2), &po));
+    UTRI_TRY(utri_scratch(g, SCR_GSZ, sizeof(int64_t) * (size_t)(2 * n), &pz));
     UTRI_TRY(utri_scratch(g, SCR_GQ, sizeof(int64_t) * 16, &pq));
-    UTRI_TRY(utri_fill_u64(pq, 0, 16, s));
-    int32_t* wcnt = (int32_t*)pc;
-    int32_t* bcnt = wcnt + n;
-    int32_t* hcnt = bcnt + n;
-    int64_t* woff = (int64_t*)po;
-    int64_t* boff = woff + n;
-    int64_t* hoff = boff + n;
-    int64_t* cnt = (int64_t*)pq;
-    const int nblk = (int)((n + TPB - 1) / TPB);
-    hipLaunchKernelGGL(k_grad_rows, dim3(nblk), dim3(TPB), 0, s, g->s_off, n, wcnt, bcnt, hcnt);
+    int32_t* c_aw = (int32_t*)pc;
+    int32_t* c_ab = c_aw + n;
+    int32_t* c_bw = c_ab + n;
+    int32_t* c_bb = c_bw + n;
+    int64_t* f_aw = (int64_t*)po;
+    int64_t* f_ab = f_aw + n;
+    int64_t* f_bw = f_ab + n;
+    int64_t* f_bb = f_bw + n;
+    int64_t* pa_off = f_bb + n;        // n + 1
+    int64_t* pb_off = pa_off + n + 1;  // n + 1
+    int64_t* sz_a = (int64_t*)pz;
+    int64_t* sz_b = sz_a + n;
+    int64_t* tot = (int64_t*)pq;       // [0, 4): item counts
+    unsigned long long* qctr = (unsigned long long*)(tot + 8);
+    hipLaunchKernelGGL(k_g_counts, dim3(nblocks(n)), dim3(TPB), 0, s, g->o_off, g->s_off, n, c_aw,
+                       c_ab, c_bw, c_bb, sz_a, sz_b);
     UTRI_HIP_TRY(hipGetLastError());
-    UTRI_TRY(utri_scan_i32(g, wcnt, woff, n, cnt, s));
-    UTRI_TRY(utri_scan_i32(g, bcnt, boff, n, cnt + 1, s));
-    UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, cnt + 2, s));
-    hipLaunchKernelGGL(k_grad_items, dim3(nblk), dim3(TPB), 0, s, (const int32_t*)wcnt,
-                       (const int32_t*)bcnt, (const int32_t*)hcnt, (const int64_t*)woff,
-                       (const int64_t*)boff, (const int64_t*)hoff, n, (int64_t*)pi);
+    UTRI_TRY(utri_scan_i32(g, c_aw, f_aw, n, tot + 0, s));
+    UTRI_TRY(utri_scan_i32(g, c_ab, f_ab, n, tot + 1, s));
+    UTRI_TRY(utri_scan_i32(g, c_bw, f_bw, n, tot + 2, s));
+    UTRI_TRY(utri_scan_i32(g, c_bb, f_bb, n, tot + 3, s));
+    UTRI_TRY(utri_scan_i64(g, sz_a, pa_off, n, pa_off + n, s));
+    UTRI_TRY(utri_scan_i64(g, sz_b, pb_off, n, pb_off + n, s));
+    // item counts and slice totals depend on the degrees only: read them once per graph
+    if (g->grad_sizes[0] < 0) {
+        int64_t h[6];
+        UTRI_HIP_TRY(hipMemcpyAsync(h, tot, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
+        UTRI_HIP_TRY(hipMemcpyAsync(h + 4, pa_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        UTRI_HIP_TRY(hipMemcpyAsync(h + 5, pb_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        UTRI_HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < 6; i++) g->grad_sizes[i] = h[i];
+    }
+    const int64_t* gs = g->grad_sizes;
+    const int64_t n_items = gs[0] + gs[1] + gs[2] + gs[3];
+    void *pi, *pp;
+    UTRI_TRY(utri_scratch(g, SCR_GITEMS, sizeof(int64_t) * (size_t)(n_items + 1), &pi));
+    UTRI_TRY(utri_scratch(g, SCR_GPART, sizeof(ulonglong2) * (size_t)(gs[4] + gs[5] + 1), &pp));
+    hipLaunchKernelGGL(k_g_items, dim3(nblocks(n)), dim3(TPB), 0, s, g->o_off, (const int32_t*)c_aw,
+                       (const int32_t*)c_ab, (const int32_t*)c_bw, (const int32_t*)c_bb,
+                       (const int64_t*)f_aw, (const int64_t*)f_ab, (const int64_t*)f_bw,
+                       (const int64_t*)f_bb, n, gs[0], gs[0] + gs[1], gs[0] + gs[1] + gs[2],
+                       (int64_t*)pi);
     UTRI_HIP_TRY(hipGetLastError());
+    UTRI_TRY(utri_fill_u64(qctr, 0, 4, s));
     GradParams P;
+    P.o_off = g->o_off;
+    P.o_adj = g->o_adj;
+    P.o_d = g->o_d;
+    P.o_eid = g->o_eid;
     P.s_off = g->s_off;
     P.s_adj = g->s_adj;
     P.s_d = g->s_d;
-    P.s_eid = g->s_eid;
-    P.h_off = g->h_off;
-    P.h_slot = g->h_slot;
-    P.grad = grad;
+    P.idmask = g->idmask;
+    P.pa_off = pa_off;
+    P.pb_off = pb_off;
+    P.pa = (ulonglong2*)pp;
+    P.pb = (ulonglong2*)pp + gs[4];
     P.items = (const int64_t*)pi;
-    P.cnt = cnt;
-    P.qctr = (unsigned long long*)(cnt + 4);
+    P.n_aw = gs[0];
+    P.n_ab = gs[1];
+    P.n_bw = gs[2];
+    P.n_bb = gs[3];
+    P.qctr = qctr;
+    P.grad = grad;
     P.n = n;
-    const int blocks = g->num_cu * grad_blocks_per_cu(g, k_grad);
-    hipLaunchKernelGGL(k_grad, dim3(blocks), dim3(TPB), 0, s, P);
+    const int blocks = g->num_cu * grad_blocks_per_cu(g, k_grad2);
+    hipLaunchKernelGGL(k_grad2, dim3(blocks), dim3(TPB), 0, s, P);
+    UTRI_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_g_final, dim3((unsigned)((n + WPB - 1) / WPB)), dim3(TPB), 0, s, P);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

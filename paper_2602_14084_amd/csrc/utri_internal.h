@@ -75,10 +75,12 @@ enum UtriScratch {
     SCR_OUT,          // int64 small device results
     SCR_SEED,         // u64 seed of the captured batch
     SCR_HIST2,        // u64 walk histogram of the batch
-    SCR_GCNT,         // int32 [3n] gradient items per owner (wave, work-group, hub)
-    SCR_GOFF,         // int64 [3n] gradient item offsets
+    SCR_GCNT,         // int32 [4n] gradient items per vertex (four lists)
+    SCR_GOFF,         // int64 [6n+2] gradient item offsets and partial-slice offsets
+    SCR_GSZ,          // int64 [2n] gradient partial-slice sizes
     SCR_GITEMS,       // int64 gradient items
     SCR_GQ,           // int64 [16] gradient item counts and work-queue counters
+    SCR_GPART,        // gradient partial sums (pairs of 64-bit half sums)
     SCR_COUNT
 };
 
@@ -137,6 +139,10 @@ struct utri_graph {
     int walk_blocks_per_cu = 0;     // 0: the kernel's resident occupancy
     int sample_blocks_per_cu = 8;
     int sample_chunk = 2048;
+
+    // gradient: item counts of its four lists and partial-slice totals (they depend on the
+    // degrees only), -1 = not read yet
+    int64_t grad_sizes[6] = {-1, -1, -1, -1, -1, -1};
 
     // event timing of the counting walk kernel (utri_timing)
     int timing = 0;

@@ -41,24 +41,10 @@ constexpr int HSH = SLOTSH * CAPH;    // work-group table slots (buckets of 4)
 #ifndef UTRI_WALK_UNR_MAX
 #define UTRI_WALK_UNR_MAX 4        // loads in flight per lane on long target rows
 #endif
-#ifndef UTRI_WALK_HASH24
-#define UTRI_WALK_HASH24 0         // 1: full-rate 24-bit multiplicative hash; 0: 32-bit
-#endif
 #ifndef UTRI_WALK_DYNAMIC
 #define UTRI_WALK_DYNAMIC 1        // 1: items handed out by atomic work queues; 0: static stride
 #endif
 
-// bucket of w in a table of 2^lg buckets (lg >= 1)
-__device__ __forceinline__ uint32_t walk_hash(int32_t w, int lg) {
-#if UTRI_WALK_HASH24
-    // the 24-bit multiplier runs at full rate (the 32-bit one at quarter rate); ids above
-    // 2^24 fold their high bits in. __umul24 returns a signed int: shift the unsigned value
-    const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 24);
-    return (uint32_t)__umul24(x, 0x9E3779u) >> (32 - lg);
-#else
-    return utri_hash32(w, lg);
-#endif
-}
 
 inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
 
@@ -209,27 +195,9 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             const int j = j0 + k * UTRI_WAVE + lane;
             const uint32_t w = pw[k] & wp.idmask;
             bool is_b = false, is_u = false;
-            // linear probe over 4-slot buckets until the key or a bucket with an empty
-            // slot. Empty slots hold 0, whose id part (vertex 0, the lowest rank) is in no
-            // oriented row, so it never matches w. Slots of a bucket fill in order, so its
-            // last slot tells whether the bucket is full.
             // kk: the matching packed key, 0 if none; h: its slot
-            uint32_t b = walk_hash((int32_t)w, R.lg);
-            int kk, h;
-            for (;;) {
-                const int4 kv = *reinterpret_cast<const int4*>(R.key + 4 * b);
-                const bool f0 = ((uint32_t)kv.x & wp.idmask) == w;
-                const bool f1 = ((uint32_t)kv.y & wp.idmask) == w;
-                const bool f2 = ((uint32_t)kv.z & wp.idmask) == w;
-                const bool f3 = ((uint32_t)kv.w & wp.idmask) == w;
-                kk = f0 ? kv.x : f1 ? kv.y : f2 ? kv.z : f3 ? kv.w : 0;
-                h = 4 * (int)b + (f0 ? 0 : f1 ? 1 : f2 ? 2 : 3);
-                // keep the results in registers here: otherwise the compiler carries the
-                // four match flags out of the loop as scalar lane masks
-                asm volatile("" : "+v"(kk), "+v"(h));
-                if (kk != 0 || kv.w == 0) break;
-                b = (b + 1) & R.mask;
-            }
+            int h;
+            const int kk = bucket_find(R.key, R.lg, R.mask, w, wp.idmask, h);
             if (j < lvs && kk != 0) {
                 const uint32_t hkey = (uint32_t)kk;
                 if (MODE == WALK_STATS) {
@@ -342,34 +310,7 @@ __device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t
     }
 }
 
-// Stage `cl` source entries starting at o_adj[base] into an open-addressing table of
-// 2^lg buckets of 4 slots; `tid` / `nthreads` are the caller's lanes (one wave or one
-// work-group). Each entry takes the first free slot of the first bucket (from its home
-// bucket on) that has one; slots are claimed in order, so a bucket's slots fill in order.
-__device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, int64_t base, int cl,
-                                            int32_t* key, uint16_t* pos, int lg, int tid,
-                                            int nthreads, uint32_t idmask) {
-    const uint32_t mask = (1u << lg) - 1u;
-    for (int j = tid; j < cl; j += nthreads) {
-        // the key is the packed word (id and d code); its id is at least 1, so it is
-        // never 0, the empty marker and the probe's not-found value
-        const int32_t pw = o_adj[base + j];
-        uint32_t b = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
-        for (;;) {
-            int s = 0;
-            while (s < 4 && atomicCAS(&key[4 * b + s], 0, pw) != 0) s++;
-            if (s < 4) { pos[4 * b + s] = (uint16_t)j; break; }
-            b = (b + 1) & mask;
-        }
-    }
-}
 
-// log2 of the bucket count of a table for cl entries: 4 * 2^lg >= slots * cl, 2^lg >= 2
-__device__ __forceinline__ int table_lg(int cl, int slots) {
-    int lg = 1;
-    while ((4 << lg) < slots * cl) lg++;
-    return lg;
-}
 
 // Wave item: source row u with 2 <= len <= CAP, staged in the wave's own table.
 template <int MODE>

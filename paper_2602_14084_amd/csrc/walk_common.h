@@ -1,4 +1,5 @@
-// walk_common.h -- per-wave LDS layouts and the edge-sampling work unit shared by the
+// walk_common.h -- the LDS bucket tables (hash, staging, probe) shared by the walk and the
+// gradient passes, per-wave LDS layouts, and the edge-sampling work unit shared by the
 // sampler kernels and the fused batch kernel.
 #pragma once
 
@@ -22,6 +23,77 @@ constexpr int HS = SLOTS * CAP;     // LDS table slots, in buckets of 4
 static_assert((CAP & (CAP - 1)) == 0 && (SLOTS & (SLOTS - 1)) == 0 && SLOTS * CAP >= 8,
               "table sizes are powers of two");
 constexpr int NB = 65;         // histogram bins (nt + 1 <= 65)
+
+#ifndef UTRI_WALK_HASH24
+#define UTRI_WALK_HASH24 0         // 1: full-rate 24-bit multiplicative hash; 0: 32-bit
+#endif
+
+// bucket of w in a table of 2^lg buckets (lg >= 1)
+__device__ __forceinline__ uint32_t walk_hash(int32_t w, int lg) {
+#if UTRI_WALK_HASH24
+    // the 24-bit multiplier runs at full rate (the 32-bit one at quarter rate); ids above
+    // 2^24 fold their high bits in. __umul24 returns a signed int: shift the unsigned value
+    const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 24);
+    return (uint32_t)__umul24(x, 0x9E3779u) >> (32 - lg);
+#else
+    return utri_hash32(w, lg);
+#endif
+}
+
+// Stage `cl` source entries starting at o_adj[base] into an open-addressing table of
+// 2^lg buckets of 4 slots; `tid` / `nthreads` are the caller's lanes (one wave or one
+// work-group). Each entry takes the first free slot of the first bucket (from its home
+// bucket on) that has one; slots are claimed in order, so a bucket's slots fill in order.
+__device__ __forceinline__ void stage_table(const int32_t* __restrict__ o_adj, int64_t base, int cl,
+                                            int32_t* key, uint16_t* pos, int lg, int tid,
+                                            int nthreads, uint32_t idmask) {
+    const uint32_t mask = (1u << lg) - 1u;
+    for (int j = tid; j < cl; j += nthreads) {
+        // the key is the packed word (id and d code); its id is at least 1, so it is
+        // never 0, the empty marker and the probe's not-found value
+        const int32_t pw = o_adj[base + j];
+        uint32_t b = walk_hash((int32_t)((uint32_t)pw & idmask), lg);
+        for (;;) {
+            int s = 0;
+            while (s < 4 && atomicCAS(&key[4 * b + s], 0, pw) != 0) s++;
+            if (s < 4) { pos[4 * b + s] = (uint16_t)j; break; }
+            b = (b + 1) & mask;
+        }
+    }
+}
+
+// log2 of the bucket count of a table for cl entries: 4 * 2^lg >= slots * cl, 2^lg >= 2
+__device__ __forceinline__ int table_lg(int cl, int slots) {
+    int lg = 1;
+    while ((4 << lg) < slots * cl) lg++;
+    return lg;
+}
+
+// Find packed key with id w in a table of 2^lg buckets of 4 slots (mask = 2^lg - 1):
+// linear probe over buckets until the key or a bucket with an empty slot. Empty slots hold
+// 0, whose id part (vertex 0, the lowest rank) is in no oriented row, so it never matches
+// w; slots of a bucket fill in order, so its last slot tells whether the bucket is full.
+// Returns the key (0 if absent) and its slot in h.
+__device__ __forceinline__ int bucket_find(const int32_t* key, int lg, uint32_t mask, uint32_t w,
+                                           uint32_t idmask, int& h) {
+    uint32_t b = walk_hash((int32_t)w, lg);
+    int kk;
+    for (;;) {
+        const int4 kv = *reinterpret_cast<const int4*>(key + 4 * b);
+        const bool f0 = ((uint32_t)kv.x & idmask) == w;
+        const bool f1 = ((uint32_t)kv.y & idmask) == w;
+        const bool f2 = ((uint32_t)kv.z & idmask) == w;
+        const bool f3 = ((uint32_t)kv.w & idmask) == w;
+        kk = f0 ? kv.x : f1 ? kv.y : f2 ? kv.z : f3 ? kv.w : 0;
+        h = 4 * (int)b + (f0 ? 0 : f1 ? 1 : f2 ? 2 : 3);
+        // keep the results in registers here: otherwise the compiler carries the four
+        // match flags out of the loop as scalar lane masks
+        asm volatile("" : "+v"(kk), "+v"(h));
+        if (kk != 0 || kv.w == 0) break;
+        b = (b + 1) & mask;
+    }
+    return kk;
+}
 
 // LDS of one wave of the walk: the staged source chunk as an open-addressing table of
 // 4-slot buckets (one 16-byte LDS read per bucket)

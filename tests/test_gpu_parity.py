@@ -185,6 +185,18 @@ def test_grad_hub_rows_match_oracle():
     assert np.array_equal(g.expected_grad().cpu().numpy(), oracle.load(n, lo, hi, p2).grad())
 
 
+def test_grad_multi_chunk_rows_match_oracle():
+    # a dense graph: oriented rows longer than one 1024-entry work-group chunk
+    n, lo, hi = inputs.random_graph(1200, 0.9, 44)
+    deg = np.bincount(np.concatenate([lo, hi]), minlength=n)
+    assert np.sort(deg)[n // 10] > 1024
+    p = inputs.draw_p(lo.shape[0], "uniform", 45)
+    og = oracle.load(n, lo, hi, p)
+    say("grad", "dense1200", "m", lo.shape[0])
+    g = gpu_graph(n, lo, hi, p)
+    assert np.array_equal(g.expected_grad().cpu().numpy(), og.grad())
+
+
 def test_autograd_function_and_set_p():
     n, lo, hi = inputs.chung_lu_graph(500, 2.5, 4000.0, 12)
     p0 = inputs.draw_p(lo.shape[0], "uniform", 1)
