@@ -36,10 +36,10 @@ namespace {
 #define UTRI_GRAD_SLOTS 4       // wave-table slots per staged entry
 #endif
 #ifndef UTRI_GRAD_CAPH
-#define UTRI_GRAD_CAPH 1024     // row chunk staged by one work-group
+#define UTRI_GRAD_CAPH 512      // row chunk staged by one work-group
 #endif
 #ifndef UTRI_GRAD_SLOTS_WG
-#define UTRI_GRAD_SLOTS_WG 2    // work-group-table slots per staged entry
+#define UTRI_GRAD_SLOTS_WG 4    // work-group-table slots per staged entry
 #endif
 #ifndef UTRI_GRAD_SPAN
 #define UTRI_GRAD_SPAN 256      // symmetric-row positions scanned by one pass-B item
@@ -56,7 +56,7 @@ static_assert((GCAP & (GCAP - 1)) == 0 && (GCAPH & (GCAPH - 1)) == 0 && GCAP <= 
               "table sizes are powers of two; item ranges are whole strips");
 
 // An oriented row has at most sqrt(2m) < 2^16 entries (its entries have at least its own
-// degree), so a row has at most 64 chunks; a symmetric row has fewer than 2^23 ranges.
+// degree), so a row has at most 128 chunks; a symmetric row has fewer than 2^23 ranges.
 // Pass-B work-group items pack (vertex, range, chunk) as 32 + 24 + 8 bits.
 constexpr int RANGE_SHIFT = 32, CHUNK_SHIFT = 56;
 
