@@ -550,17 +550,24 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
                                                const int64_t* __restrict__ n_items_dev,
                                                SampleParams sp, SampleGraph G,
                                                const int32_t* __restrict__ slen, int64_t units) {
-    __shared__ WalkShared S;
+    // the walk's tables and the sampler's strip buffers are used one after the other
+    union BatchLds {
+        WalkShared walk;
+        SegLds seg[WPB];
+    };
+    __shared__ BatchLds S;
     __shared__ HistLds hlds[WPB];
-    __shared__ SegLds slds[WPB];
     const int wib = threadIdx.x / UTRI_WAVE;
     HistLds* H = &hlds[wib];
     for (int q = utri_lane(); q < 2 * NB; q += UTRI_WAVE) H->hist[q / NB][q % NB] = 0;
     utri_wave_sync();
     WalkLaneState st;
-    if (wp.acc != nullptr)
+    if (wp.acc != nullptr) {
         walk_phases<WALK_HIST>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                               n_items_dev[1], S, H, st);
+                               n_items_dev[1], S.walk, H, st);
+        walk_flush<WALK_HIST>(wp, o_d, H, st);
+    }
+    __syncthreads();  // the walk's tables are no longer read; the strip buffers reuse them
     const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
     const int64_t W = (int64_t)gridDim.x * WPB;
     const int64_t upw = (sp.k + sp.chunk - 1) / sp.chunk;  // units per world
@@ -569,9 +576,8 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
         const int64_t part = u % upw;
         const int64_t i0 = part * sp.chunk;
         const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
-        sample_unit(sp, G, slen, world, i0, i1, slds[wib]);
+        sample_unit(sp, G, slen, world, i0, i1, S.seg[wib]);
     }
-    if (wp.acc != nullptr) walk_flush<WALK_HIST>(wp, o_d, H, st);
 }
 
 }  // namespace
