@@ -176,6 +176,18 @@ int count_impl(utri_graph* g, double t, int method, int64_t out[2], hipStream_t 
 }
 
 // Launch sequence of the batch path (also what gets captured into a hipGraph).
+int64_t n_draws(const SampleParams& sp) { return (int64_t)sp.worlds * sp.k; }
+
+// Grouped sampling of draws [t_begin, worlds * k), one pass of g->sample_pass at a time.
+int sample_passes(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t_begin,
+                  hipStream_t s) {
+    for (int64_t t0 = t_begin; t0 < n_draws(sp); t0 += g->sample_pass) {
+        UTRI_TRY(utri_sample_prepare(g, sp, slen, t0, std::min<int64_t>(n_draws(sp), t0 + g->sample_pass), s));
+        UTRI_TRY(utri_sample_launch(g, sp, slen, s));
+    }
+    return UTRI_OK;
+}
+
 int batch_sequence(utri_graph* g, const double* dc, const int32_t* dord, int nt, double cmin,
                    int64_t k, int32_t worlds, const uint64_t* seed_dev, int64_t* exact,
                    double* est, hipStream_t s) {
@@ -206,6 +218,7 @@ int batch_sequence(utri_graph* g, const double* dc, const int32_t* dord, int nt,
         sp.worlds = worlds;
         sp.chunk = g->sample_chunk;
         sp.hist = (unsigned long long*)hs;
+        UTRI_TRY(utri_sample_prepare(g, sp, slen, 0, std::min<int64_t>(n_draws(sp), g->sample_pass), s));
     }
     if (!items) {
         // no walk part: the kernel still needs a valid (zero) item count
@@ -214,6 +227,8 @@ int batch_sequence(utri_graph* g, const double* dc, const int32_t* dord, int nt,
         nitems = (int64_t*)pn;
     }
     UTRI_TRY(utri_batch_launch(g, wp, items, nitems, len, 0, sp, slen, s));
+    // draws beyond the first pass in further launches
+    if (sp.hist) UTRI_TRY(sample_passes(g, sp, slen, g->sample_pass, s));
     if (exact) UTRI_TRY(utri_finalize_launch((const unsigned long long*)hw, 1, nt, dord, g->m, 1, exact, nullptr, s));
     if (sp.hist) UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k, nullptr, est, s));
     return UTRI_OK;
@@ -274,6 +289,8 @@ int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int
     if (rc != UTRI_OK) return rc;
     apply_cache(g, getenv("UTRI_TUNE_CACHE"));
     if (const char* e = getenv("UTRI_WALK_BLOCKS_PER_CU")) g->walk_blocks_per_cu = std::max(0, atoi(e));
+    if (const char* e = getenv("UTRI_SAMPLE_PASS"))
+        g->sample_pass = std::max<int64_t>(64, std::min<int64_t>(UTRI_SAMPLE_PASS, atoll(e)));
     *out = g;
     return UTRI_OK;
 }
@@ -501,7 +518,7 @@ int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t world
     sp.worlds = worlds;
     sp.chunk = g->sample_chunk;
     sp.hist = (unsigned long long*)hs;
-    UTRI_TRY(utri_sample_launch(g, sp, slen, s));
+    UTRI_TRY(sample_passes(g, sp, slen, 0, s));
     UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k,
                                   nullptr, est, s));
     UTRI_HIP_TRY(hipStreamSynchronize(s));
@@ -649,7 +666,7 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
         if (tot < best) { best = tot; best_b = b; }
     }
     g->walk_blocks_per_cu = best_b;
-    // sampler work-unit size
+    // draws per sampler group item
     std::vector<double> tv{t};
     double* est = nullptr;
     const int32_t worlds = 64;
@@ -657,7 +674,7 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
     UTRI_HIP_TRY(hipMalloc(&est, sizeof(double) * worlds * 2));
     float best_s = 1e30f;
     int best_c = g->sample_chunk;
-    for (int c : {256, 1024, 4096}) {
+    for (int c : {64, 128, 256, 512}) {
         g->sample_chunk = c;
         int rc = utri_sample(g, tv.data(), 1, k, worlds, 12345, UTRI_SAMPLE_EDGE, est, hip_stream);
         if (rc != UTRI_OK) { (void)hipFree(est); return rc; }

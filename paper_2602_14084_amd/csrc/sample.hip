@@ -4,8 +4,10 @@
 //
 // Local search of a sampled edge e = (a, b): nothing if |d_e| < c (Lemma 2); else the
 // Absolute-Edge-Order prefix (|d| >= c) of the shorter row is streamed and each
-// neighbour is looked up in the other row's hash table. That mirrors the improved
-// local search, whose cost is the pruned degree of the cheaper endpoint (Theorem 6.3).
+// neighbour is looked up in the other row. That mirrors the improved local search, whose
+// cost is the pruned degree of the cheaper endpoint (Theorem 6.3). The estimator groups a
+// pass of draws by the looked-up endpoint first (counting sort: count, scan, scatter) so a
+// group's row is staged once (walk_common.h).
 #include <algorithm>
 
 #include "walk_common.h"
@@ -33,21 +35,74 @@ __global__ void k_symlen(const int64_t* __restrict__ off, const double* __restri
     len[v] = (int32_t)(lo - a);
 }
 
+// Draw t of the pass: world t / k, index t % k. Returns false when the draw cannot close a
+// triangle (|d_e| < cmin or an empty prefix).
+__device__ __forceinline__ bool pass_draw(const SampleParams& sp, const SampleGraph& G,
+                                          const int32_t* __restrict__ slen, int64_t t, int64_t& e,
+                                          int32_t& world, int32_t& y) {
+    const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
+    world = (int32_t)(t / sp.k);
+    const int64_t i = t - (int64_t)world * sp.k;
+    e = utri_sample_edge(seed, (uint32_t)world, (uint64_t)i, G.m);
+    if (fabs(G.e_d[e]) < sp.cmin) return false;
+    int32_t x;
+    int lx;
+    draw_ends(G, slen, e, x, y, lx);
+    return lx > 0;
+}
+
+__global__ void k_s_count(SampleParams sp, SampleGraph G, const int32_t* __restrict__ slen,
+                          int32_t* __restrict__ cnt) {
+    const int64_t t = sp.t0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sp.t1) return;
+    int64_t e;
+    int32_t world, y;
+    if (pass_draw(sp, G, slen, t, e, world, y)) atomicAdd(&cnt[y], 1);
+}
+
+// Each draw takes a distinct slot of its group (the count is consumed downwards).
+__global__ void k_s_scatter(SampleParams sp, SampleGraph G, const int32_t* __restrict__ slen,
+                            int32_t* __restrict__ cnt, int64_t* __restrict__ rec) {
+    const int64_t t = sp.t0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sp.t1) return;
+    int64_t e;
+    int32_t world, y;
+    if (!pass_draw(sp, G, slen, t, e, world, y)) return;
+    const int slot = atomicSub(&cnt[y], 1) - 1;
+    rec[sp.goff[y] + slot] = e | ((int64_t)world << 32);
+}
+
+// Items per group: ceil(draws / chunk), as work-group items when the probed prefix fits a
+// work-group table but not a wave table, as wave items when it fits a wave table, and as
+// hub items (work-group items probing the global table) when it fits neither.
+__global__ void k_s_icount(const int64_t* __restrict__ goff, const int32_t* __restrict__ slen,
+                           int64_t n, int chunk, int32_t* __restrict__ cb, int32_t* __restrict__ cw,
+                           int32_t* __restrict__ ch) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    const int64_t c = goff[y + 1] - goff[y];
+    const int32_t ns = (int32_t)((c + chunk - 1) / chunk);
+    const int L = slen[y];
+    cb[y] = (L > SCAP && L <= SCAPH) ? ns : 0;
+    cw[y] = L <= SCAP ? ns : 0;
+    ch[y] = L > SCAPH ? ns : 0;
+}
+
+__global__ void k_s_ifill(const int32_t* __restrict__ cb, const int32_t* __restrict__ cw,
+                          const int32_t* __restrict__ ch, const int64_t* __restrict__ ob,
+                          const int64_t* __restrict__ ow, const int64_t* __restrict__ oh, int64_t n,
+                          int64_t wave_base, int64_t hub_base, int64_t* __restrict__ items) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    for (int q = 0; q < cb[y]; q++) items[ob[y] + q] = y | ((int64_t)q << 32);
+    for (int q = 0; q < cw[y]; q++) items[wave_base + ow[y] + q] = y | ((int64_t)q << 32);
+    for (int q = 0; q < ch[y]; q++) items[hub_base + oh[y] + q] = y | ((int64_t)q << 32);
+}
+
 __global__ void __launch_bounds__(TPB) k_sample(SampleParams sp, SampleGraph G,
-                                                const int32_t* __restrict__ slen, int64_t units) {
-    __shared__ SegLds lds[WPB];
-    const int wib = threadIdx.x / UTRI_WAVE;
-    SegLds& L = lds[wib];
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
-    const int64_t W = (int64_t)gridDim.x * WPB;
-    const int64_t upw = (sp.k + sp.chunk - 1) / sp.chunk;
-    for (int64_t u = gw; u < units; u += W) {
-        const int32_t world = (int32_t)(u / upw);
-        const int64_t part = u % upw;
-        const int64_t i0 = part * sp.chunk;
-        const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
-        sample_unit(sp, G, slen, world, i0, i1, L);
-    }
+                                                const int32_t* __restrict__ slen) {
+    __shared__ SampleLds S;
+    sample_groups(sp, G, slen, S);
 }
 
 // one wave per listed edge: out[i][j][0/1] = local counts at threshold j (original order)
@@ -132,12 +187,71 @@ static SampleGraph sample_graph(utri_graph* g) {
                        g->h_off, g->h_slot};
 }
 
+int utri_sample_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t0,
+                        int64_t t1, hipStream_t s) {
+    const int64_t n = g->n;
+    const int64_t draws = t1 - t0;
+    // items of one list: at most ceil(c / chunk) <= c / chunk + 1 per non-empty group
+    const int64_t bound = draws / sp.chunk + std::min<int64_t>(n, draws) + 1;
+    void *pc, *po, *pr, *pic, *pio, *pit, *pq;
+    UTRI_TRY(utri_scratch(g, SCR_SCNT, sizeof(int32_t) * (size_t)(n + 2), &pc));
+    UTRI_TRY(utri_scratch(g, SCR_SOFF, sizeof(int64_t) * (size_t)(n + 1), &po));
+    UTRI_TRY(utri_scratch(g, SCR_SREC, sizeof(int64_t) * (size_t)(draws + 1), &pr));
+    UTRI_TRY(utri_scratch(g, SCR_SICNT, sizeof(int32_t) * (size_t)(3 * n), &pic));
+    UTRI_TRY(utri_scratch(g, SCR_SIOFF, sizeof(int64_t) * (size_t)(3 * n), &pio));
+    UTRI_TRY(utri_scratch(g, SCR_SITEMS, sizeof(int64_t) * (size_t)(3 * bound), &pit));
+    UTRI_TRY(utri_scratch(g, SCR_SQ, sizeof(int64_t) * 16, &pq));
+    int32_t* cnt = (int32_t*)pc;
+    int64_t* goff = (int64_t*)po;
+    int32_t* cb = (int32_t*)pic;
+    int32_t* cw = cb + n;
+    int32_t* ch = cw + n;
+    int64_t* ob = (int64_t*)pio;
+    int64_t* ow = ob + n;
+    int64_t* oh = ow + n;
+    int64_t* q = (int64_t*)pq;
+    sp.t0 = t0;
+    sp.t1 = t1;
+    sp.rec = (const int64_t*)pr;
+    sp.goff = goff;
+    sp.items = (const int64_t*)pit;
+    sp.nitems = q;
+    sp.wave_base = bound;
+    sp.hub_base = 2 * bound;
+    sp.qctr = (unsigned long long*)(q + 4);  // q[4, 14)
+    UTRI_TRY(utri_fill_u64(cnt, 0, (n + 2) / 2, s));
+    UTRI_TRY(utri_fill_u64(q, 0, 16, s));
+    const SampleGraph G = sample_graph(g);
+    if (draws > 0) {
+        hipLaunchKernelGGL(k_s_count, dim3(blocks_for(draws)), dim3(TPB), 0, s, sp, G, slen, cnt);
+        UTRI_HIP_TRY(hipGetLastError());
+    }
+    UTRI_TRY(utri_scan_i32(g, cnt, goff, n, goff + n, s));
+    if (draws > 0) {
+        hipLaunchKernelGGL(k_s_scatter, dim3(blocks_for(draws)), dim3(TPB), 0, s, sp, G, slen, cnt,
+                           (int64_t*)pr);
+        UTRI_HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_s_icount, dim3(blocks_for(n)), dim3(TPB), 0, s, (const int64_t*)goff, slen,
+                       n, sp.chunk, cb, cw, ch);
+    UTRI_HIP_TRY(hipGetLastError());
+    UTRI_TRY(utri_scan_i32(g, cb, ob, n, q, s));
+    UTRI_TRY(utri_scan_i32(g, cw, ow, n, q + 1, s));
+    UTRI_TRY(utri_scan_i32(g, ch, oh, n, q + 2, s));
+    hipLaunchKernelGGL(k_s_ifill, dim3(blocks_for(n)), dim3(TPB), 0, s, (const int32_t*)cb,
+                       (const int32_t*)cw, (const int32_t*)ch, (const int64_t*)ob,
+                       (const int64_t*)ow, (const int64_t*)oh, n, bound, 2 * bound, (int64_t*)pit);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
 int utri_sample_launch(utri_graph* g, const SampleParams& sp, const int32_t* slen, hipStream_t s) {
-    if (g->m == 0 || sp.k <= 0 || sp.worlds <= 0) return UTRI_OK;
-    const int64_t units = (int64_t)sp.worlds * ((sp.k + sp.chunk - 1) / sp.chunk);
-    const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * g->sample_blocks_per_cu,
-                                              (units + WPB - 1) / WPB);
-    hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(TPB), 0, s, sp, sample_graph(g), slen, units);
+    if (g->m == 0 || sp.t1 <= sp.t0) return UTRI_OK;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample, TPB, 0) != hipSuccess || nb < 1)
+        nb = 4;
+    const int blocks = g->num_cu * std::min(nb, g->sample_blocks_per_cu);
+    hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(TPB), 0, s, sp, sample_graph(g), slen);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

@@ -25,6 +25,8 @@
 // readable entries the oriented id array carries past its last row: a row stream loads
 // whole groups of up to 8 strips of 64 without clamping to the row end
 #define UTRI_ROW_PAD 512
+// most sampler draws grouped per pass (records of 8 bytes each)
+#define UTRI_SAMPLE_PASS (1ll << 27)
 
 // ------------------------------------------------------------------ error plumbing
 
@@ -81,6 +83,13 @@ enum UtriScratch {
     SCR_GITEMS,       // int64 gradient items
     SCR_GQ,           // int64 [16] gradient item counts and work-queue counters
     SCR_GPART,        // gradient partial sums (pairs of 64-bit half sums)
+    SCR_SCNT,         // int32 [n+2] sampler draws per probed endpoint
+    SCR_SOFF,         // int64 [n+1] sampler group offsets
+    SCR_SREC,         // int64 sampler draw records of one pass
+    SCR_SICNT,        // int32 [2n] sampler items per group (work-group, wave)
+    SCR_SIOFF,        // int64 [2n] sampler item offsets
+    SCR_SITEMS,       // int64 sampler items
+    SCR_SQ,           // int64 [8] sampler item counts and work-queue counters
     SCR_COUNT
 };
 
@@ -138,7 +147,8 @@ struct utri_graph {
     // launch shape (set by the autotuner, else defaults)
     int walk_blocks_per_cu = 0;     // 0: the kernel's resident occupancy
     int sample_blocks_per_cu = 8;
-    int sample_chunk = 2048;
+    int sample_chunk = 128;         // draws per sampler group item
+    int64_t sample_pass = UTRI_SAMPLE_PASS;  // draws grouped per sampler pass
 
     // gradient: item counts of its four lists and partial-slice totals (they depend on the
     // degrees only), -1 = not read yet
@@ -346,11 +356,23 @@ struct SampleParams {
     const uint64_t* seed_dev = nullptr;  // if set, the seed is read from device memory
     int64_t k = 0;
     int32_t worlds = 0;
-    int chunk = 2048;               // samples per work unit (multiple of 64)
+    int chunk = 128;                // draws per group item
     unsigned long long* hist = nullptr;  // [worlds][2][nt+1]
+    // draws of one pass grouped by the probed endpoint (set by utri_sample_prepare)
+    int64_t t0 = 0, t1 = 0;              // flat draw range [t0, t1), t = world * k + i
+    const int64_t* rec = nullptr;        // edge | world << 32, grouped by probed endpoint
+    const int64_t* goff = nullptr;       // [n+1] group offsets into rec
+    const int64_t* items = nullptr;      // work-group, wave and hub items: y | sub << 32
+    const int64_t* nitems = nullptr;     // device: # work-group, # wave, # hub items
+    int64_t wave_base = 0;               // first wave item in items
+    int64_t hub_base = 0;                // first hub item in items
+    unsigned long long* qctr = nullptr;  // ten work-queue counters, zeroed per pass
 };
 
 int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen);
+// Group the draws [t0, t1) by probed endpoint and build the pass's items into sp.
+int utri_sample_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t0,
+                        int64_t t1, hipStream_t s);
 int utri_sample_launch(utri_graph* g, const SampleParams& sp, const int32_t* slen, hipStream_t s);
 int utri_batch_launch(utri_graph* g, const WalkParams& wp, const int64_t* items,
                       const int64_t* n_items_dev, const int32_t* len, int64_t n_items_bound,

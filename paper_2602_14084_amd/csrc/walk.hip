@@ -540,7 +540,8 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
 }
 
 // Fused batch: the walk (threshold histogram of every triangle at the smallest
-// threshold) followed by edge-sampling units, in one persistent launch.
+// threshold) followed by the grouped edge-sampling items of the first pass, in one
+// persistent launch.
 __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __restrict__ o_off,
                                                const int32_t* __restrict__ o_adj,
                                                const double* __restrict__ o_d,
@@ -549,11 +550,11 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
                                                const int64_t* __restrict__ items,
                                                const int64_t* __restrict__ n_items_dev,
                                                SampleParams sp, SampleGraph G,
-                                               const int32_t* __restrict__ slen, int64_t units) {
-    // the walk's tables and the sampler's strip buffers are used one after the other
+                                               const int32_t* __restrict__ slen) {
+    // the walk's tables and the sampler's tables are used one after the other
     union BatchLds {
         WalkShared walk;
-        SegLds seg[WPB];
+        SampleLds samp;
     };
     __shared__ BatchLds S;
     __shared__ HistLds hlds[WPB];
@@ -567,17 +568,8 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
                                n_items_dev[1], S.walk, H, st);
         walk_flush<WALK_HIST>(wp, o_d, H, st);
     }
-    __syncthreads();  // the walk's tables are no longer read; the strip buffers reuse them
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
-    const int64_t W = (int64_t)gridDim.x * WPB;
-    const int64_t upw = (sp.k + sp.chunk - 1) / sp.chunk;  // units per world
-    for (int64_t u = gw; u < units; u += W) {
-        const int32_t world = (int32_t)(u / upw);
-        const int64_t part = u % upw;
-        const int64_t i0 = part * sp.chunk;
-        const int64_t i1 = std::min<int64_t>(sp.k, i0 + sp.chunk);
-        sample_unit(sp, G, slen, world, i0, i1, S.seg[wib]);
-    }
+    __syncthreads();  // the walk's tables are no longer read; the sampler's reuse them
+    if (sp.hist != nullptr && sp.t1 > sp.t0) sample_groups(sp, G, slen, S.samp);
 }
 
 }  // namespace
@@ -681,13 +673,11 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     set_launch_fields(g, wp);
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
-    const int64_t units = (sp.hist != nullptr && sp.k > 0)
-                              ? (int64_t)sp.worlds * ((sp.k + sp.chunk - 1) / sp.chunk) : 0;
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
                   g->h_slot};
     const int blocks = g->num_cu * blocks_per_cu(g, k_batch);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj, g->o_d,
-                       len, g->perm, items, n_items_dev, sp, G, slen, units);
+                       len, g->perm, items, n_items_dev, sp, G, slen);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

@@ -106,27 +106,6 @@ struct HistLds {
     unsigned long long hist[2][NB];
 };
 
-// LDS of one wave of a flattened strip loop (sampler, backward)
-struct SegLds {
-    int32_t end[UTRI_WAVE];       // inclusive prefix of segment lengths
-    int64_t xoff[UTRI_WAVE];      // start of the streamed row of each segment
-    int64_t yoff[UTRI_WAVE];      // start of the probe-side row
-    int64_t hoff[UTRI_WAVE];      // start of the probe-side table
-    int32_t hlg[UTRI_WAVE];       // log2 size of the probe-side table
-    double dseg[UTRI_WAVE];       // d of the segment's own edge
-    unsigned long long shist[2][NB];
-};
-
-__device__ inline int seg_search(const int32_t* end, int f) {
-    // smallest index i with end[i] > f (end is non-decreasing and end[63] > f)
-    int lo = 0, hi = UTRI_WAVE - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (end[mid] > f) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
-
 // wave-uniform broadcast of lane `src` (src must be wave-uniform)
 __device__ inline int bcast_i32(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
 __device__ inline int64_t bcast_i64(int64_t x, int src) {
@@ -170,73 +149,277 @@ __device__ inline int log2_size(int64_t size) {
     return lg;
 }
 
-// One work unit of the edge-sampling estimator: samples [i_begin, i_end) of `world`.
-// Each sampled edge e = (a, b) with |d_e| >= cmin streams the Absolute-Edge-Order
-// prefix (|d| >= cmin) of its shorter row and probes the other row's hash table; the
-// triangles found are classified and binned by threshold into the wave's histogram,
-// which is added to hist[world][2][nt+1] at the end of the unit.
-__device__ inline void sample_unit(const SampleParams& sp, const SampleGraph& G,
-                                   const int32_t* __restrict__ slen, int32_t world,
-                                   int64_t i_begin, int64_t i_end, SegLds& L) {
+// ------------------------------------------------------------------ grouped edge sampling
+//
+// A sampled edge e = (x, y) with |d_e| >= cmin streams the Absolute-Edge-Order prefix
+// (|d| >= cmin) of the endpoint with the shorter prefix, x, and looks every entry up in
+// the other endpoint's row, y; each triangle found is classified and binned by threshold
+// into the draw's histogram, added to hist[world][2][nt+1] when the draw ends. Draws are
+// grouped by y beforehand (a counting sort), so a group stages y's prefix once: in the LDS
+// of one wave (<= SCAP entries) or of one work-group (<= SCAPH), else y's global hash
+// table is probed while the group's draws keep it in cache.
+
+#ifndef UTRI_SAMPLE_CAP
+#define UTRI_SAMPLE_CAP 128
+#endif
+#ifndef UTRI_SAMPLE_CAPH
+#define UTRI_SAMPLE_CAPH 1024
+#endif
+constexpr int SCAP = UTRI_SAMPLE_CAP;    // probed-row prefixes staged by one wave
+constexpr int SCAPH = UTRI_SAMPLE_CAPH;  // probed-row prefixes staged by one work-group
+constexpr int SSL = 4;                   // table slots per staged entry (load factor 1/4)
+static_assert((SCAP & (SCAP - 1)) == 0 && (SCAPH & (SCAPH - 1)) == 0 && SCAP <= SCAPH &&
+                  SCAPH <= 65536,
+              "table sizes are powers of two; positions are 16-bit");
+
+struct SampleWaveLds {
+    alignas(16) int32_t key[SCAP * SSL];  // neighbour id + 1 (0 = empty)
+    uint16_t pos[SCAP * SSL];
+    uint32_t rh[2][NB];                   // histogram of the current draw
+};
+struct SampleBlockLds {
+    alignas(16) int32_t key[SCAPH * SSL];
+    uint16_t pos[SCAPH * SSL];
+    uint32_t rh[WPB][2][NB];
+};
+union SampleLds {
+    SampleWaveLds wave[WPB];
+    SampleBlockLds block;
+};
+
+// Stage the first cl entries of the symmetric row at s_adj[base] with keys id + 1.
+__device__ __forceinline__ void stage_sym(const int32_t* __restrict__ s_adj, int64_t base, int cl,
+                                          int32_t* key, uint16_t* pos, int lg, int tid,
+                                          int nthreads) {
+    const uint32_t mask = (1u << lg) - 1u;
+    for (int j = tid; j < cl; j += nthreads) {
+        const int32_t w1 = s_adj[base + j] + 1;
+        uint32_t b = walk_hash(w1, lg);
+        for (;;) {
+            int s = 0;
+            while (s < 4 && atomicCAS(&key[4 * b + s], 0, w1) != 0) s++;
+            if (s < 4) { pos[4 * b + s] = (uint16_t)j; break; }
+            b = (b + 1) & mask;
+        }
+    }
+}
+
+// Endpoints of edge e: x has the shorter prefix (ties by id), lx its length.
+__device__ __forceinline__ void draw_ends(const SampleGraph& G, const int32_t* __restrict__ slen,
+                                          int64_t e, int32_t& x, int32_t& y, int& lx) {
+    const int32_t a = G.inv[G.e_lo[e]], b = G.inv[G.e_hi[e]];
+    const int la = slen[a], lb = slen[b];
+    const bool ax = (la < lb) || (la == lb && a < b);
+    x = ax ? a : b;
+    y = ax ? b : a;
+    lx = ax ? la : lb;
+}
+
+// Stream x's prefix [sx, sx + lx) against y's staged prefix (or y's global table) and bin
+// the triangles into rh. UNR strips of loads (and, for global tables, their first table
+// slots) are in flight before any is used; lanes past the row end re-load its last entry
+// and drop the result.
+template <bool GLOBAL_TABLE, int UNR>
+__device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGraph& G,
+                                         const int32_t* key, const uint16_t* pos, int lg,
+                                         uint32_t mask, int64_t hoff, int64_t sy, int64_t sx,
+                                         int lx, double de, uint32_t (*rh)[NB]) {
     const int lane = utri_lane();
-    for (int q = lane; q < 2 * NB; q += UTRI_WAVE) L.shist[q / NB][q % NB] = 0;
-    utri_wave_sync();
-    const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
-    for (int64_t i0 = i_begin; i0 < i_end; i0 += UTRI_WAVE) {
-        const int64_t i = i0 + lane;
-        int work = 0;
-        int64_t xoff = 0, yoff = 0, hoff = 0;
-        int lg = 0;
-        double de = 0.0;
-        if (i < i_end) {
-            const int64_t e = utri_sample_edge(seed, (uint32_t)world, (uint64_t)i, G.m);
-            de = G.e_d[e];
-            if (fabs(de) >= sp.cmin) {
-                const int32_t a = G.inv[G.e_lo[e]], b = G.inv[G.e_hi[e]];
-                const int la = slen[a], lb = slen[b];
-                const bool ax = (la < lb) || (la == lb && a < b);
-                const int32_t x = ax ? a : b, y = ax ? b : a;
-                work = ax ? la : lb;
-                xoff = G.s_off[x];
-                yoff = G.s_off[y];
-                hoff = G.h_off[y];
-                lg = log2_size(G.h_off[y + 1] - hoff);
+    for (int j0 = 0; j0 < lx; j0 += UNR * UTRI_WAVE) {
+        int32_t w[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; k++) w[k] = G.s_adj[sx + min(j0 + k * UTRI_WAVE + lane, lx - 1)];
+        int64_t py[UNR];
+        if (GLOBAL_TABLE) {
+            const uint32_t gm = (1u << lg) - 1u;
+            uint32_t h[UNR];
+            uint64_t sl[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                h[k] = utri_hash32(w[k], lg);
+                sl[k] = G.h_slot[hoff + h[k]];
             }
-        }
-        const int incl = (int)utri_wave_incl_scan((int64_t)work);
-        const int total = __shfl(incl, UTRI_WAVE - 1, UTRI_WAVE);
-        L.end[lane] = incl;
-        L.xoff[lane] = xoff;
-        L.yoff[lane] = yoff;
-        L.hoff[lane] = hoff;
-        L.hlg[lane] = lg;
-        L.dseg[lane] = de;
-        utri_wave_sync();
-        for (int f0 = 0; f0 < total; f0 += UTRI_WAVE) {
-            const int f = f0 + lane;
-            if (f < total) {
-                const int sg = seg_search(L.end, f);
-                const int start = sg ? L.end[sg - 1] : 0;
-                const int64_t px = L.xoff[sg] + (f - start);
-                const int32_t w = G.s_adj[px];
-                const int64_t py = sym_lookup(G.h_slot, L.hoff[sg], L.hlg[sg], w);
-                if (py >= 0) {
-                    const double s = utri_tri_s(L.dseg[sg], G.s_d[px], G.s_d[L.yoff[sg] + py]);
-                    bool bal;
-                    const int bin = utri_bin_of(s, sp.cvals, sp.nt, bal);
-                    if (bin > 0) atomicAdd(&L.shist[bal ? 0 : 1][bin], 1ull);
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                while (sl[k] != ~0ull && (int32_t)(sl[k] >> 32) != w[k]) {
+                    h[k] = (h[k] + 1) & gm;
+                    sl[k] = G.h_slot[hoff + h[k]];
                 }
+                py[k] = (sl[k] != ~0ull) ? (int64_t)(uint32_t)(sl[k] & 0xFFFFFFFFull) : -1;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                int h;
+                const int kk = bucket_find(key, lg, mask, (uint32_t)w[k] + 1u, 0xFFFFFFFFu, h);
+                py[k] = kk != 0 ? (int64_t)pos[h] : -1;
             }
         }
-        utri_wave_sync();
+#pragma unroll
+        for (int k = 0; k < UNR; k++) {
+            const int j = j0 + k * UTRI_WAVE + lane;
+            if (j < lx && py[k] >= 0) {
+                const double s = utri_tri_s(de, G.s_d[sx + j], G.s_d[sy + py[k]]);
+                bool bal;
+                const int bin = utri_bin_of(s, sp.cvals, sp.nt, bal);
+                if (bin > 0) atomicAdd(&rh[bal ? 0 : 1][bin], 1u);
+            }
+        }
     }
-    for (int q = lane; q < 2 * NB; q += UTRI_WAVE) {
-        const int cls = q / NB, bin = q % NB;
-        const unsigned long long v = L.shist[cls][bin];
-        if (v && bin <= sp.nt)
-            atomicAdd(&sp.hist[((int64_t)world * 2 + cls) * (sp.nt + 1) + bin], v);
+}
+
+template <bool GLOBAL_TABLE>
+__device__ __forceinline__ void draw_row_any(const SampleParams& sp, const SampleGraph& G,
+                                             const int32_t* key, const uint16_t* pos, int lg,
+                                             uint32_t mask, int64_t hoff, int64_t sy, int64_t sx,
+                                             int lx, double de, uint32_t (*rh)[NB]) {
+    if (lx > 2 * UTRI_WAVE)
+        draw_row<GLOBAL_TABLE, 4>(sp, G, key, pos, lg, mask, hoff, sy, sx, lx, de, rh);
+    else if (lx > UTRI_WAVE)
+        draw_row<GLOBAL_TABLE, 2>(sp, G, key, pos, lg, mask, hoff, sy, sx, lx, de, rh);
+    else
+        draw_row<GLOBAL_TABLE, 1>(sp, G, key, pos, lg, mask, hoff, sy, sx, lx, de, rh);
+}
+
+// Add the draw's histogram to its world's and clear it.
+__device__ __forceinline__ void draw_flush(const SampleParams& sp, int32_t world, uint32_t (*rh)[NB]) {
+    utri_wave_sync();
+    const int nb = sp.nt + 1;
+    for (int q = utri_lane(); q < 2 * nb; q += UTRI_WAVE) {
+        const int cls = q / nb, bin = q % nb;
+        const uint32_t v = rh[cls][bin];
+        if (v) {
+            atomicAdd(&sp.hist[((int64_t)world * 2 + cls) * nb + bin], (unsigned long long)v);
+            rh[cls][bin] = 0;
+        }
     }
     utri_wave_sync();
+}
+
+// The draws [r0, r1) of group y whose index is part mod nparts, 64 loaded at a time.
+template <bool GLOBAL_TABLE>
+__device__ __forceinline__ void group_draws(const SampleParams& sp, const SampleGraph& G,
+                                            const int32_t* __restrict__ slen, int32_t y, int64_t r0,
+                                            int64_t r1, const int32_t* key, const uint16_t* pos,
+                                            int lg, uint32_t mask, int64_t hoff, uint32_t (*rh)[NB],
+                                            int part, int nparts) {
+    const int lane = utri_lane();
+    const int64_t sy = G.s_off[y];
+    for (int64_t b0 = r0; b0 < r1; b0 += UTRI_WAVE) {
+        const int64_t r = b0 + lane;
+        int64_t sx = 0;
+        int lx = 0;
+        double de = 0.0;
+        int32_t world = 0;
+        if (r < r1) {
+            const int64_t rec = sp.rec[r];
+            const int64_t e = rec & 0xFFFFFFFFll;
+            world = (int32_t)(rec >> 32);
+            int32_t x, yy;
+            draw_ends(G, slen, e, x, yy, lx);
+            de = G.e_d[e];
+            sx = G.s_off[x];
+        }
+        const int nr = (int)min((int64_t)UTRI_WAVE, r1 - b0);
+        for (int si = part; si < nr; si += nparts) {
+            draw_row_any<GLOBAL_TABLE>(sp, G, key, pos, lg, mask, hoff, sy, bcast_i64(sx, si),
+                                       bcast_i32(lx, si), bcast_f64(de, si), rh);
+            draw_flush(sp, bcast_i32(world, si), rh);
+        }
+    }
+}
+
+// One group item: draws [sub * chunk, sub * chunk + chunk) of group y. Work-group items
+// split the draws over the four waves and stage y's prefix in the work-group table
+// (SCAP < prefix <= SCAPH) or, for longer prefixes, probe y's global hash table; wave
+// items stage it in the wave's table (prefix <= SCAP).
+__device__ inline void sample_item(const SampleParams& sp, const SampleGraph& G,
+                                   const int32_t* __restrict__ slen, int64_t item, bool block,
+                                   SampleLds& S) {
+    const int wib = threadIdx.x / UTRI_WAVE;
+    const int lane = utri_lane();
+    const int32_t y = (int32_t)(item & 0xFFFFFFFF);
+    const int64_t sub = item >> 32;
+    const int Ly = slen[y];
+    const int64_t r0 = sp.goff[y] + sub * sp.chunk;
+    const int64_t r1 = min(sp.goff[y + 1], r0 + (int64_t)sp.chunk);
+    if (block && Ly > SCAPH) {
+        SampleBlockLds& B = S.block;
+        const int64_t hoff = G.h_off[y];
+        const int hlg = log2_size(G.h_off[y + 1] - hoff);
+        __syncthreads();  // the previous item's flushes are done
+        for (int q = threadIdx.x; q < WPB * 2 * NB; q += TPB) (&B.rh[0][0][0])[q] = 0;
+        __syncthreads();
+        group_draws<true>(sp, G, slen, y, r0, r1, nullptr, nullptr, hlg, 0, hoff, B.rh[wib], wib,
+                          WPB);
+        return;
+    }
+    if (block) {
+        SampleBlockLds& B = S.block;
+        const int lg = table_lg(Ly, SSL);
+        const int nbk = 1 << lg;
+        __syncthreads();  // the previous item's probes are done
+        for (int i = threadIdx.x; i < 4 * nbk; i += TPB) B.key[i] = 0;
+        for (int q = threadIdx.x; q < WPB * 2 * NB; q += TPB) (&B.rh[0][0][0])[q] = 0;
+        __syncthreads();
+        stage_sym(G.s_adj, G.s_off[y], Ly, B.key, B.pos, lg, threadIdx.x, TPB);
+        __syncthreads();
+        group_draws<false>(sp, G, slen, y, r0, r1, B.key, B.pos, lg, (uint32_t)(nbk - 1), 0,
+                           B.rh[wib], wib, WPB);
+        return;
+    }
+    SampleWaveLds& W = S.wave[wib];
+    for (int q = lane; q < 2 * NB; q += UTRI_WAVE) (&W.rh[0][0])[q] = 0;
+    const int lg = table_lg(Ly, SSL);
+    const int nbk = 1 << lg;
+    for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) W.key[i] = 0;
+    utri_wave_sync();
+    stage_sym(G.s_adj, G.s_off[y], Ly, W.key, W.pos, lg, lane, UTRI_WAVE);
+    utri_wave_sync();
+    group_draws<false>(sp, G, slen, y, r0, r1, W.key, W.pos, lg, (uint32_t)(nbk - 1), 0, W.rh, 0,
+                       1);
+    utri_wave_sync();  // probes done before the next item clears the table
+}
+
+// All group items of a pass, heaviest groups (highest ids) first: hub items from eight
+// queues, one per XCD (work-group index mod 8, the hardware's round-robin placement), so
+// each XCD works through its own few hubs and keeps their tables in its L2; then the other
+// work-group items (one queue); then wave items in groups of four.
+__device__ inline void sample_groups(const SampleParams& sp, const SampleGraph& G,
+                                     const int32_t* __restrict__ slen, SampleLds& S) {
+    __shared__ int64_t s_qs;
+    const int64_t nb = sp.nitems[0], nw = sp.nitems[1], nh = sp.nitems[2];
+    const int xcd = (int)(blockIdx.x % 8);
+    for (int qq = 0; qq < 8; qq++) {
+        const int q8 = (xcd + qq) % 8;
+        const int64_t a = nh * q8 / 8, b = nh * (q8 + 1) / 8;
+        for (;;) {
+            if (threadIdx.x == 0) s_qs = (int64_t)atomicAdd(&sp.qctr[2 + q8], 1ull);
+            __syncthreads();
+            const int64_t t = s_qs;
+            __syncthreads();
+            if (a + t >= b) break;
+            sample_item(sp, G, slen, sp.items[sp.hub_base + nh - 1 - (a + t)], true, S);
+        }
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_qs = (int64_t)atomicAdd(&sp.qctr[0], 1ull);
+        __syncthreads();
+        const int64_t q = s_qs;
+        __syncthreads();
+        if (q >= nb) break;
+        sample_item(sp, G, slen, sp.items[nb - 1 - q], true, S);
+    }
+    __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
+    for (;;) {
+        int64_t base = 0;
+        if (utri_lane() == 0) base = (int64_t)atomicAdd(&sp.qctr[1], 4ull);
+        base = bcast_i64(base, 0);
+        if (base >= nw) break;
+        const int64_t end = base + 4 < nw ? base + 4 : nw;
+        for (int64_t q = base; q < end; q++)
+            sample_item(sp, G, slen, sp.items[sp.wave_base + nw - 1 - q], false, S);
+    }
 }
 
 }  // namespace utri_dev

@@ -244,6 +244,26 @@ def test_sampler_replays_oracle_exactly():
             assert np.array_equal(est, oest), (name, ts)
 
 
+def test_sampler_groups_and_passes(monkeypatch):
+    # probed rows of every class (wave tables, work-group tables, hub rows through their
+    # global tables), then the same draws cut into passes of 1,000
+    n, lo, hi = inputs.rmat_graph(15, seed=3)
+    p = inputs.draw_p(lo.shape[0], "uniform", 47)
+    og = oracle.load(n, lo, hi, p)
+    ts, k, W, seed = [0.55, 0.7], 3000, 7, 99
+    want, _ = og.sample(ts, k, W, seed)
+    say("sample groups rmat15")
+    g = gpu_graph(n, lo, hi, p)
+    assert np.array_equal(g.sample(ts, k, W, seed).cpu().numpy(), want)
+    monkeypatch.setenv("UTRI_SAMPLE_PASS", "1000")
+    g2 = gpu_graph(n, lo, hi, p)  # the pass size is read when the graph is loaded
+    say("sample passes rmat15")
+    assert np.array_equal(g2.sample(ts, k, W, seed).cpu().numpy(), want)
+    ex, es = g2.batch(ts, k, W, seed, use_graph=False)
+    assert np.array_equal(es.cpu().numpy(), want)
+    assert np.array_equal(ex.cpu().numpy(), og.count_multi(ts))
+
+
 def test_batch_eager_and_graph_replays():
     n, lo, hi = inputs.rmat_graph(13, seed=9)
     p = inputs.draw_p(lo.shape[0], "beta22", 2)
