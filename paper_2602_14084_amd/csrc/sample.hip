@@ -102,6 +102,7 @@ __global__ void k_s_ifill(const int32_t* __restrict__ cb, const int32_t* __restr
 __global__ void __launch_bounds__(TPB) k_sample(SampleParams sp, SampleGraph G,
                                                 const int32_t* __restrict__ slen) {
     __shared__ SampleLds S;
+    thresh_stage(sp.cvals, sp.nt);
     sample_groups(sp, G, slen, S);
 }
 
@@ -115,6 +116,7 @@ __global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double*
     const int lane = utri_lane();
     const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
     const int64_t W = (int64_t)gridDim.x * WPB;
+    thresh_stage(cv, nt);
     for (int64_t q = gw; q < k; q += W) {
         for (int t = lane; t < 2 * NB; t += UTRI_WAVE) hist[wib][t / NB][t % NB] = 0;
         utri_wave_sync();
@@ -126,14 +128,14 @@ __global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double*
         const int32_t x = ax ? a : b, y = ax ? b : a;
         const int64_t lx = ax ? la : lb;
         const int64_t xoff = G.s_off[x], yoff = G.s_off[y], hoff = G.h_off[y];
-        const int lg = log2_size(G.h_off[y + 1] - hoff);
+        const int lg = hbuckets_lg(G, y);
         for (int64_t j = lane; j < lx; j += UTRI_WAVE) {
             const int32_t w = G.s_adj[xoff + j];
-            const int64_t py = sym_lookup(G.h_slot, hoff, lg, w);
+            const int64_t py = sym_lookup(G.h_tab, hoff, lg, w);
             if (py >= 0) {
                 const double s = utri_tri_s(de, G.s_d[xoff + j], G.s_d[yoff + py]);
                 bool bal;
-                const int bin = utri_bin_of(s, cv, nt, bal);
+                const int bin = thresh_bin(s, bal);
                 if (bin > 0) atomicAdd(&hist[wib][bal ? 0 : 1][bin], 1ull);
             }
         }
@@ -184,7 +186,7 @@ int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen
 
 static SampleGraph sample_graph(utri_graph* g) {
     return SampleGraph{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d,
-                       g->h_off, g->h_slot};
+                       g->h_off, g->h_tab};
 }
 
 int utri_sample_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t0,

@@ -8,8 +8,10 @@
 //       each row in Absolute Edge Order  s_d f64 [2m], s_eid int32 [2m]
 //       (|d| descending, then neighbour id ascending; Section 5), so the entries
 //       with |d| >= c of any row form a prefix.
-//   per-row open-addressing tables      h_off int64 [n+1], h_slot u64 [sum of sizes]
-//       slot = (neighbour << 32) | position in the row; size = pow2 >= 2*deg.
+//   per-row bucketed hash tables        h_off int64 [n+1] (slots), h_tab u32 [2 * sum]
+//       buckets of 8 slots, 64 bytes each: 8 keys (neighbour id, ~0 = empty) then the 8
+//       entries' positions in the row; slots fill in order; size = pow2 >= max(3*deg, 8),
+//       a load factor of at most 1/3, so a lookup almost always reads one bucket.
 //   oriented rows u -> v (v > u)        o_off int64 [n+1], o_adj int32 [m],
 //       same Absolute Edge Order         o_d f64 [m], o_eid int32 [m]
 #pragma once
@@ -124,7 +126,7 @@ struct utri_graph {
     int32_t* s_row = nullptr;    // row of each symmetric entry
 
     int64_t* h_off = nullptr;
-    uint64_t* h_slot = nullptr;
+    uint32_t* h_tab = nullptr;
     int64_t h_total = 0;
 
     int64_t* o_off = nullptr;
@@ -222,6 +224,35 @@ __device__ inline uint32_t utri_hash32(int32_t key, int lg) {
     return ((uint32_t)key * 0x9E3779B1u) >> (32 - lg);
 }
 
+// Per-row global tables: slots per bucket and the table size for a row of deg entries.
+constexpr int UTRI_HB = 8;
+__host__ __device__ inline int64_t utri_htable_slots(int64_t deg) {
+    if (deg <= 0) return 0;
+    int64_t size = UTRI_HB;
+    while (size < 3 * deg) size <<= 1;
+    return size;
+}
+
+// Home bucket of key in a table of 2^lgb buckets (lgb >= 0).
+__device__ inline uint32_t utri_hbucket(int32_t key, int lgb) {
+    return lgb > 0 ? utri_hash32(key, lgb) : 0u;
+}
+
+// Slot of key among the 8 keys of a bucket (two 16-byte words), or -1.
+__device__ __forceinline__ int utri_hmatch(const uint4& a, const uint4& b, int32_t key) {
+    const uint32_t k = (uint32_t)key;
+    int s = -1;
+    s = a.x == k ? 0 : s;
+    s = a.y == k ? 1 : s;
+    s = a.z == k ? 2 : s;
+    s = a.w == k ? 3 : s;
+    s = b.x == k ? 4 : s;
+    s = b.y == k ? 5 : s;
+    s = b.z == k ? 6 : s;
+    s = b.w == k ? 7 : s;
+    return s;
+}
+
 __device__ inline void utri_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -289,20 +320,6 @@ __device__ inline int64_t utri_sample_edge(uint64_t seed, uint32_t world, uint64
                 (uint32_t)(seed >> 32), x);
     uint64_t x64 = ((uint64_t)x[1] << 32) | (uint64_t)x[0];
     return (int64_t)__umul64hi(x64, (uint64_t)m);
-}
-
-// number of thresholds c_j (sorted ascending, nt of them) that the value s passes:
-// for s <= 0, #{j : c_j <= -s} (balanced at every j below it); for s > 0, #{j : c_j < s}.
-__device__ inline int utri_bin_of(double s, const double* cv, int nt, bool& bal) {
-    bal = (s <= 0.0);
-    double key = bal ? -s : s;
-    int lo = 0, hi = nt;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        bool pass = bal ? (cv[mid] <= key) : (cv[mid] < key);
-        if (pass) lo = mid + 1; else hi = mid;
-    }
-    return lo;
 }
 
 // ------------------------------------------------------------------ kernels (host launchers)

@@ -213,7 +213,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                         if (!kCoded) {
                             if (MODE == WALK_HIST) {
                                 bool bal;
-                                const int bin = utri_bin_of(s, wp.cvals, wp.nt, bal);
+                                const int bin = thresh_bin(s, bal);
                                 if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
                             } else if (MODE == WALK_EXPECTED) {
                                 const int64_t t = utri_fix62(s);
@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
     HistLds* H = &hlds[MODE == WALK_HIST ? wib : 0];
     if (MODE == WALK_HIST) {
         for (int q = utri_lane(); q < 2 * NB; q += UTRI_WAVE) H->hist[q / NB][q % NB] = 0;
-        utri_wave_sync();
+        thresh_stage(wp.cvals, wp.nt);
     }
     WalkLaneState st;
     walk_phases<MODE>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0], n_items_dev[1], S,
@@ -561,7 +561,9 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
     const int wib = threadIdx.x / UTRI_WAVE;
     HistLds* H = &hlds[wib];
     for (int q = utri_lane(); q < 2 * NB; q += UTRI_WAVE) H->hist[q / NB][q % NB] = 0;
-    utri_wave_sync();
+    // the walk and the sampler share the thresholds
+    if (wp.acc != nullptr) thresh_stage(wp.cvals, wp.nt);
+    else thresh_stage(sp.cvals, sp.nt);
     WalkLaneState st;
     if (wp.acc != nullptr) {
         walk_phases<WALK_HIST>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
@@ -674,7 +676,7 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
-                  g->h_slot};
+                  g->h_tab};
     const int blocks = g->num_cu * blocks_per_cu(g, k_batch);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj, g->o_d,
                        len, g->perm, items, n_items_dev, sp, G, slen);

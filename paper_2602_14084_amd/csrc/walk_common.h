@@ -106,6 +106,49 @@ struct HistLds {
     unsigned long long hist[2][NB];
 };
 
+// ------------------------------------------------------------------ threshold bins
+//
+// The bin of a triangle value s is the number of sorted thresholds c_j it passes
+// (balanced: c_j <= -s for s <= 0; unbalanced: c_j < s for s > 0). A work-group stages the
+// thresholds in LDS with a grid over [0, 1]: cell g = min(floor(key * TG), TG - 1) of
+// key = |s|, and base[g] = the number of thresholds below cell g (negative ones, or whose
+// own cell is smaller), all of which key passes; only the thresholds in key's own cell
+// (none or one for thresholds spread over [0, 1]) are compared. The result equals a
+// binary search over the thresholds, comparison for comparison.
+constexpr int TG = 512;
+static_assert(NB - 1 <= 255, "base counts are bytes");
+struct ThreshLds {
+    double c[NB];
+    uint8_t base[TG + 1];
+};
+__shared__ ThreshLds thr_lds;
+
+__device__ __forceinline__ int thresh_cell(double x) {
+    return x < 0.0 ? -1 : min((int)(x * (double)TG), TG - 1);
+}
+
+// All threads of the work-group call this (it synchronises the work-group).
+__device__ inline void thresh_stage(const double* __restrict__ cv, int nt) {
+    for (int j = threadIdx.x; j < nt; j += blockDim.x) thr_lds.c[j] = cv[j];
+    __syncthreads();
+    for (int g = threadIdx.x; g <= TG; g += blockDim.x) {
+        int cnt = 0;
+        for (int j = 0; j < nt; j++) cnt += thresh_cell(thr_lds.c[j]) < g ? 1 : 0;
+        thr_lds.base[g] = (uint8_t)cnt;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int thresh_bin(double s, bool& bal) {
+    bal = (s <= 0.0);
+    const double key = bal ? -s : s;
+    const int g = thresh_cell(key);
+    int b = thr_lds.base[g];
+    const int e = thr_lds.base[g + 1];
+    while (b < e && (bal ? thr_lds.c[b] <= key : thr_lds.c[b] < key)) b++;
+    return b;
+}
+
 // wave-uniform broadcast of lane `src` (src must be wave-uniform)
 __device__ inline int bcast_i32(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
 __device__ inline int64_t bcast_i64(int64_t x, int src) {
@@ -127,26 +170,40 @@ struct SampleGraph {
     const int32_t* s_adj;
     const double* s_d;
     const int64_t* h_off;
-    const uint64_t* h_slot;
+    const uint32_t* h_tab;
 };
-
-// position of w in the symmetric row whose table starts at hoff with 2^lg slots, or -1
-__device__ inline int64_t sym_lookup(const uint64_t* __restrict__ h_slot, int64_t hoff, int lg,
-                                     int32_t w) {
-    const uint32_t mask = (1u << lg) - 1u;
-    uint32_t h = utri_hash32(w, lg);
-    for (;;) {
-        const uint64_t sl = h_slot[hoff + h];
-        if (sl == ~0ull) return -1;
-        if ((int32_t)(sl >> 32) == w) return (int64_t)(uint32_t)(sl & 0xFFFFFFFFull);
-        h = (h + 1) & mask;
-    }
-}
 
 __device__ inline int log2_size(int64_t size) {
     int lg = 0;
     while ((1ll << lg) < size) lg++;
     return lg;
+}
+
+// log2 of the bucket count of row y's global table
+__device__ inline int hbuckets_lg(const SampleGraph& G, int32_t y) {
+    return log2_size((G.h_off[y + 1] - G.h_off[y]) / UTRI_HB);
+}
+
+// Bucket b (two 16-byte key words) of the table at slot offset hoff.
+__device__ __forceinline__ const uint4* hbucket_ptr(const uint32_t* __restrict__ tab, int64_t hoff,
+                                                    uint32_t b) {
+    return (const uint4*)(tab + 2 * (hoff + (int64_t)b * UTRI_HB));
+}
+
+// Position of w in the symmetric row whose table (2^lgb buckets) starts at slot hoff, or -1.
+// A bucket whose last slot is empty ends the search (slots fill in order).
+__device__ inline int64_t sym_lookup(const uint32_t* __restrict__ tab, int64_t hoff, int lgb,
+                                     int32_t w) {
+    const uint32_t mask = (1u << lgb) - 1u;
+    uint32_t b = utri_hbucket(w, lgb);
+    for (;;) {
+        const uint4* p = hbucket_ptr(tab, hoff, b);
+        const uint4 k0 = p[0], k1 = p[1];
+        const int s = utri_hmatch(k0, k1, w);
+        if (s >= 0) return (int64_t)((const uint32_t*)p)[UTRI_HB + s];
+        if (k1.w == 0xFFFFFFFFu) return -1;
+        b = (b + 1) & mask;
+    }
 }
 
 // ------------------------------------------------------------------ grouped edge sampling
@@ -231,21 +288,29 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
         for (int k = 0; k < UNR; k++) w[k] = G.s_adj[sx + min(j0 + k * UTRI_WAVE + lane, lx - 1)];
         int64_t py[UNR];
         if (GLOBAL_TABLE) {
+            // lg: log2 of the bucket count; a bucket's positions follow its keys
             const uint32_t gm = (1u << lg) - 1u;
-            uint32_t h[UNR];
-            uint64_t sl[UNR];
+            uint32_t b[UNR];
+            uint4 k0[UNR], k1[UNR];
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
-                h[k] = utri_hash32(w[k], lg);
-                sl[k] = G.h_slot[hoff + h[k]];
+                b[k] = utri_hbucket(w[k], lg);
+                const uint4* p = hbucket_ptr(G.h_tab, hoff, b[k]);
+                k0[k] = p[0];
+                k1[k] = p[1];
             }
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
-                while (sl[k] != ~0ull && (int32_t)(sl[k] >> 32) != w[k]) {
-                    h[k] = (h[k] + 1) & gm;
-                    sl[k] = G.h_slot[hoff + h[k]];
+                int s = utri_hmatch(k0[k], k1[k], w[k]);
+                while (s < 0 && k1[k].w != 0xFFFFFFFFu) {
+                    b[k] = (b[k] + 1) & gm;
+                    const uint4* p = hbucket_ptr(G.h_tab, hoff, b[k]);
+                    k0[k] = p[0];
+                    k1[k] = p[1];
+                    s = utri_hmatch(k0[k], k1[k], w[k]);
                 }
-                py[k] = (sl[k] != ~0ull) ? (int64_t)(uint32_t)(sl[k] & 0xFFFFFFFFull) : -1;
+                py[k] = s >= 0 ? (int64_t)((const uint32_t*)hbucket_ptr(G.h_tab, hoff, b[k]))[UTRI_HB + s]
+                               : -1;
             }
         } else {
 #pragma unroll
@@ -261,7 +326,7 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
             if (j < lx && py[k] >= 0) {
                 const double s = utri_tri_s(de, G.s_d[sx + j], G.s_d[sy + py[k]]);
                 bool bal;
-                const int bin = utri_bin_of(s, sp.cvals, sp.nt, bal);
+                const int bin = thresh_bin(s, bal);
                 if (bin > 0) atomicAdd(&rh[bal ? 0 : 1][bin], 1u);
             }
         }
@@ -346,7 +411,7 @@ __device__ inline void sample_item(const SampleParams& sp, const SampleGraph& G,
     if (block && Ly > SCAPH) {
         SampleBlockLds& B = S.block;
         const int64_t hoff = G.h_off[y];
-        const int hlg = log2_size(G.h_off[y + 1] - hoff);
+        const int hlg = hbuckets_lg(G, y);
         __syncthreads();  // the previous item's flushes are done
         for (int q = threadIdx.x; q < WPB * 2 * NB; q += TPB) (&B.rh[0][0][0])[q] = 0;
         __syncthreads();
