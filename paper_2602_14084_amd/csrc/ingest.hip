@@ -240,23 +240,22 @@ __global__ void k_hsize(const int32_t* __restrict__ deg_new, int64_t n, int64_t*
 // Entry i of the symmetric rows takes the first empty slot of the first bucket, from its
 // home bucket on, that has one; slots therefore fill in order within a bucket.
 __global__ void k_hinsert(const int32_t* __restrict__ s_row, const int32_t* __restrict__ s_adj,
-                          const int64_t* __restrict__ s_off, const int64_t* __restrict__ h_off,
-                          int64_t cnt, uint32_t* __restrict__ tab) {
+                          const double* __restrict__ s_d, const int64_t* __restrict__ h_off,
+                          int64_t cnt, uint32_t* __restrict__ hkey, double* __restrict__ hd) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
     const int32_t r = s_row[i];
     const int32_t key = s_adj[i];
-    const uint32_t pos = (uint32_t)(i - s_off[r]);
     const int64_t base = h_off[r];
     const int64_t nbk = (h_off[r + 1] - base) / UTRI_HB;
     int lgb = 0;
     while ((1ll << lgb) < nbk) lgb++;
     uint32_t b = utri_hbucket(key, lgb);
     for (;;) {
-        uint32_t* bk = tab + 2 * (base + (int64_t)b * UTRI_HB);
+        const int64_t b0 = base + (int64_t)b * UTRI_HB;
         for (int q = 0; q < UTRI_HB; q++) {
-            if (atomicCAS(&bk[q], 0xFFFFFFFFu, (uint32_t)key) == 0xFFFFFFFFu) {
-                bk[UTRI_HB + q] = pos;
+            if (atomicCAS(&hkey[b0 + q], 0xFFFFFFFFu, (uint32_t)key) == 0xFFFFFFFFu) {
+                hd[b0 + q] = s_d[i];
                 return;
             }
         }
@@ -422,9 +421,9 @@ int utri_build_rows(utri_graph* g, hipStream_t s) {
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_exclusive_scan_i64(g, hs, g->h_off, n, s));
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, g->h_off + n, g->h_total);
-    UTRI_TRY(utri_fill_u64(g->h_tab, ~0ull, g->h_total, s));  // 2 * h_total words
-    hipLaunchKernelGGL(k_hinsert, dim3(nb), dim3(TPB), 0, s, g->s_row, g->s_adj, g->s_off,
-                       g->h_off, cnt, g->h_tab);
+    UTRI_TRY(utri_fill_u64(g->h_key, ~0ull, g->h_total / 2, s));  // h_total is a multiple of 8
+    hipLaunchKernelGGL(k_hinsert, dim3(nb), dim3(TPB), 0, s, g->s_row, g->s_adj, g->s_d,
+                       g->h_off, cnt, g->h_key, g->h_d);
     UTRI_HIP_TRY(hipGetLastError());
     // temporaries are freed at scope exit; hipFree waits for the device
     UTRI_HIP_TRY(hipStreamSynchronize(s));
@@ -434,7 +433,7 @@ int utri_build_rows(utri_graph* g, hipStream_t s) {
 static void free_graph(utri_graph* g) {
     if (!g) return;
     void* ptrs[] = {g->e_lo, g->e_hi, g->e_p, g->e_d, g->perm, g->inv, g->deg_new, g->s_off,
-                    g->s_adj, g->s_d, g->s_eid, g->s_row, g->h_off, g->h_tab, g->o_off,
+                    g->s_adj, g->s_d, g->s_eid, g->s_row, g->h_off, g->h_key, g->h_d, g->o_off,
                     g->o_adj, g->o_d, g->o_eid, g->d_flags};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -585,7 +584,8 @@ static int load_impl(const int64_t* src, const int64_t* dst, const double* p, in
         for (int64_t v = 0; v < n; v++) tot += utri_htable_slots(hdeg[v]);
         g->h_total = tot;
     }
-    UTRI_TRY(dev_alloc(&g->h_tab, 2 * g->h_total));
+    UTRI_TRY(dev_alloc(&g->h_key, g->h_total));
+    UTRI_TRY(dev_alloc(&g->h_d, g->h_total));
     UTRI_TRY(utri_build_rows(g, s));
     // maximum out-degree
     if (n > 0) {

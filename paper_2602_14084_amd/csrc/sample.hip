@@ -127,13 +127,13 @@ __global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double*
         const bool ax = (la < lb) || (la == lb && a < b);
         const int32_t x = ax ? a : b, y = ax ? b : a;
         const int64_t lx = ax ? la : lb;
-        const int64_t xoff = G.s_off[x], yoff = G.s_off[y], hoff = G.h_off[y];
+        const int64_t xoff = G.s_off[x], hoff = G.h_off[y];
         const int lg = hbuckets_lg(G, y);
         for (int64_t j = lane; j < lx; j += UTRI_WAVE) {
             const int32_t w = G.s_adj[xoff + j];
-            const int64_t py = sym_lookup(G.h_tab, hoff, lg, w);
-            if (py >= 0) {
-                const double s = utri_tri_s(de, G.s_d[xoff + j], G.s_d[yoff + py]);
+            const int64_t sl = sym_lookup(G.h_key, hoff, lg, w);
+            if (sl >= 0) {
+                const double s = utri_tri_s(de, G.s_d[xoff + j], G.h_d[sl]);
                 bool bal;
                 const int bin = thresh_bin(s, bal);
                 if (bin > 0) atomicAdd(&hist[wib][bal ? 0 : 1][bin], 1ull);
@@ -186,7 +186,7 @@ int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen
 
 static SampleGraph sample_graph(utri_graph* g) {
     return SampleGraph{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d,
-                       g->h_off, g->h_tab};
+                       g->h_off, g->h_key, g->h_d};
 }
 
 int utri_sample_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t0,

@@ -8,10 +8,11 @@
 //       each row in Absolute Edge Order  s_d f64 [2m], s_eid int32 [2m]
 //       (|d| descending, then neighbour id ascending; Section 5), so the entries
 //       with |d| >= c of any row form a prefix.
-//   per-row bucketed hash tables        h_off int64 [n+1] (slots), h_tab u32 [2 * sum]
-//       buckets of 8 slots, 64 bytes each: 8 keys (neighbour id, ~0 = empty) then the 8
-//       entries' positions in the row; slots fill in order; size = pow2 >= max(3*deg, 8),
-//       a load factor of at most 1/3, so a lookup almost always reads one bucket.
+//   per-row bucketed hash tables        h_off int64 [n+1] (slots), h_key u32 [sum],
+//       h_d f64 [sum]: buckets of 8 slots (32 bytes of keys: neighbour id, ~0 = empty),
+//       and each slot's d of the edge to that neighbour; slots fill in order; size =
+//       pow2 >= max(3*deg, 8), a load factor of at most 1/3, so a lookup almost always
+//       reads one bucket.
 //   oriented rows u -> v (v > u)        o_off int64 [n+1], o_adj int32 [m],
 //       same Absolute Edge Order         o_d f64 [m], o_eid int32 [m]
 #pragma once
@@ -126,7 +127,8 @@ struct utri_graph {
     int32_t* s_row = nullptr;    // row of each symmetric entry
 
     int64_t* h_off = nullptr;
-    uint32_t* h_tab = nullptr;
+    uint32_t* h_key = nullptr;
+    double* h_d = nullptr;
     int64_t h_total = 0;
 
     int64_t* o_off = nullptr;

@@ -170,7 +170,8 @@ struct SampleGraph {
     const int32_t* s_adj;
     const double* s_d;
     const int64_t* h_off;
-    const uint32_t* h_tab;
+    const uint32_t* h_key;
+    const double* h_d;
 };
 
 __device__ inline int log2_size(int64_t size) {
@@ -184,23 +185,23 @@ __device__ inline int hbuckets_lg(const SampleGraph& G, int32_t y) {
     return log2_size((G.h_off[y + 1] - G.h_off[y]) / UTRI_HB);
 }
 
-// Bucket b (two 16-byte key words) of the table at slot offset hoff.
-__device__ __forceinline__ const uint4* hbucket_ptr(const uint32_t* __restrict__ tab, int64_t hoff,
+// Keys of bucket b (two 16-byte words) of the table at slot offset hoff.
+__device__ __forceinline__ const uint4* hbucket_ptr(const uint32_t* __restrict__ hkey, int64_t hoff,
                                                     uint32_t b) {
-    return (const uint4*)(tab + 2 * (hoff + (int64_t)b * UTRI_HB));
+    return (const uint4*)(hkey + hoff + (int64_t)b * UTRI_HB);
 }
 
-// Position of w in the symmetric row whose table (2^lgb buckets) starts at slot hoff, or -1.
+// Slot of w in the symmetric row whose table (2^lgb buckets) starts at slot hoff, or -1.
 // A bucket whose last slot is empty ends the search (slots fill in order).
-__device__ inline int64_t sym_lookup(const uint32_t* __restrict__ tab, int64_t hoff, int lgb,
+__device__ inline int64_t sym_lookup(const uint32_t* __restrict__ hkey, int64_t hoff, int lgb,
                                      int32_t w) {
     const uint32_t mask = (1u << lgb) - 1u;
     uint32_t b = utri_hbucket(w, lgb);
     for (;;) {
-        const uint4* p = hbucket_ptr(tab, hoff, b);
+        const uint4* p = hbucket_ptr(hkey, hoff, b);
         const uint4 k0 = p[0], k1 = p[1];
         const int s = utri_hmatch(k0, k1, w);
-        if (s >= 0) return (int64_t)((const uint32_t*)p)[UTRI_HB + s];
+        if (s >= 0) return hoff + (int64_t)b * UTRI_HB + s;
         if (k1.w == 0xFFFFFFFFu) return -1;
         b = (b + 1) & mask;
     }
@@ -284,18 +285,24 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
     const int lane = utri_lane();
     for (int j0 = 0; j0 < lx; j0 += UNR * UTRI_WAVE) {
         int32_t w[UNR];
+        double dx[UNR];  // loaded with the ids: the row's lines are read for the hits anyway
 #pragma unroll
-        for (int k = 0; k < UNR; k++) w[k] = G.s_adj[sx + min(j0 + k * UTRI_WAVE + lane, lx - 1)];
-        int64_t py[UNR];
+        for (int k = 0; k < UNR; k++) {
+            const int64_t j = sx + min(j0 + k * UTRI_WAVE + lane, lx - 1);
+            w[k] = G.s_adj[j];
+            dx[k] = G.s_d[j];
+        }
+        bool hit[UNR];
+        double dy[UNR];
         if (GLOBAL_TABLE) {
-            // lg: log2 of the bucket count; a bucket's positions follow its keys
+            // lg: log2 of the bucket count; a hit reads d from the slot
             const uint32_t gm = (1u << lg) - 1u;
             uint32_t b[UNR];
             uint4 k0[UNR], k1[UNR];
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
                 b[k] = utri_hbucket(w[k], lg);
-                const uint4* p = hbucket_ptr(G.h_tab, hoff, b[k]);
+                const uint4* p = hbucket_ptr(G.h_key, hoff, b[k]);
                 k0[k] = p[0];
                 k1[k] = p[1];
             }
@@ -304,27 +311,28 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
                 int s = utri_hmatch(k0[k], k1[k], w[k]);
                 while (s < 0 && k1[k].w != 0xFFFFFFFFu) {
                     b[k] = (b[k] + 1) & gm;
-                    const uint4* p = hbucket_ptr(G.h_tab, hoff, b[k]);
+                    const uint4* p = hbucket_ptr(G.h_key, hoff, b[k]);
                     k0[k] = p[0];
                     k1[k] = p[1];
                     s = utri_hmatch(k0[k], k1[k], w[k]);
                 }
-                py[k] = s >= 0 ? (int64_t)((const uint32_t*)hbucket_ptr(G.h_tab, hoff, b[k]))[UTRI_HB + s]
-                               : -1;
+                hit[k] = s >= 0;
+                dy[k] = hit[k] ? G.h_d[hoff + (int64_t)b[k] * UTRI_HB + s] : 0.0;
             }
         } else {
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
                 int h;
                 const int kk = bucket_find(key, lg, mask, (uint32_t)w[k] + 1u, 0xFFFFFFFFu, h);
-                py[k] = kk != 0 ? (int64_t)pos[h] : -1;
+                hit[k] = kk != 0;
+                dy[k] = hit[k] ? G.s_d[sy + pos[h]] : 0.0;
             }
         }
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;
-            if (j < lx && py[k] >= 0) {
-                const double s = utri_tri_s(de, G.s_d[sx + j], G.s_d[sy + py[k]]);
+            if (j < lx && hit[k]) {
+                const double s = utri_tri_s(de, dx[k], dy[k]);
                 bool bal;
                 const int bin = thresh_bin(s, bal);
                 if (bin > 0) atomicAdd(&rh[bal ? 0 : 1][bin], 1u);
