@@ -115,7 +115,7 @@ __device__ __forceinline__ int64_t fix_prod(double a, double b) {
 // Stream the oriented row [ovs, ovs + lvs) and handle every entry found in the table.
 // Pass A (row O(v), dpair = d_uv): adds d_uw * d_vw to the lane's row sum and
 // d_uv * d_vw to the hit entry. Pass B (row O(u), dpair = d_uv): adds d_uv * d_uw to the
-// hit entry. Lanes past the row end read on (the id array is padded) and are dropped.
+// hit entry. Lanes past the row end are masked off and their results dropped.
 template <bool PASS_A, int UNR>
 __device__ __forceinline__ void g_stream(const GradParams& P, const GTab& T, int64_t ovs, int lvs,
                                          double dpair, uint64_t& slo, int64_t& shi) {
@@ -127,7 +127,8 @@ __device__ __forceinline__ void g_stream(const GradParams& P, const GTab& T, int
         uint32_t pw[UNR];
         const char* lb = rowb + (((uint32_t)(j0 + lane)) << 2);
 #pragma unroll
-        for (int k = 0; k < UNR; k++) pw[k] = *(const uint32_t*)(lb + k * 4 * UTRI_WAVE);
+        for (int k = 0; k < UNR; k++)
+            pw[k] = (j0 + k * UTRI_WAVE + lane < lvs) ? *(const uint32_t*)(lb + k * 4 * UTRI_WAVE) : 0u;
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             const int j = j0 + k * UTRI_WAVE + lane;

@@ -253,7 +253,10 @@ __global__ void k_hinsert(const int32_t* __restrict__ s_row, const int32_t* __re
     uint32_t b = utri_hbucket(key, lgb);
     for (;;) {
         const int64_t b0 = base + (int64_t)b * UTRI_HB;
-        for (int q = 0; q < UTRI_HB; q++) {
+        // claim the first slot seen empty; a lost race moves on to the next one
+        int q = 0;
+        while (q < UTRI_HB && __atomic_load_n(&hkey[b0 + q], __ATOMIC_RELAXED) != 0xFFFFFFFFu) q++;
+        for (; q < UTRI_HB; q++) {
             if (atomicCAS(&hkey[b0 + q], 0xFFFFFFFFu, (uint32_t)key) == 0xFFFFFFFFu) {
                 hd[b0 + q] = s_d[i];
                 return;
