@@ -50,6 +50,11 @@ def _load():
     lib.orc_sample_edge.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64]
     lib.orc_sample_edge.restype = C.c_int64
     lib.orc_sample.argtypes = [vp, _f64p, C.c_int, C.c_int64, C.c_int32, C.c_uint64, _f64p, _i64p]
+    lib.orc_vertex_local.argtypes = [vp, _f64p, C.c_int, _i64p, C.c_int64, _i64p]
+    lib.orc_sample_vertex.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64]
+    lib.orc_sample_vertex.restype = C.c_int64
+    lib.orc_sample_vertices.argtypes = [vp, _f64p, C.c_int, C.c_int64, C.c_int32, C.c_uint64,
+                                        _f64p, _i64p]
     lib.orc_num_threads.restype = C.c_int
     _lib = lib
     return lib
@@ -206,6 +211,29 @@ class OracleGraph:
         return est, sums
 
 
+    def vertex_local(self, ts, vs=None):
+        """Local counts at each listed vertex (all vertices by default): [k][nt][2]."""
+        ts = np.atleast_1d(np.ascontiguousarray(ts, dtype=np.float64))
+        vs = np.arange(self.n, dtype=np.int64) if vs is None else np.ascontiguousarray(vs, np.int64)
+        out = np.zeros((vs.shape[0], ts.shape[0], 2), np.int64)
+        rc = self._lib.orc_vertex_local(self._h, _p(ts, _f64p), int(ts.shape[0]), _p(vs, _i64p),
+                                        int(vs.shape[0]), _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "vertex_local")
+        return out
+
+    def sample_vertices(self, ts, k, worlds, seed):
+        ts = np.atleast_1d(np.ascontiguousarray(ts, dtype=np.float64))
+        est = np.zeros((worlds, ts.shape[0], 2), np.float64)
+        sums = np.zeros((worlds, ts.shape[0], 2), np.int64)
+        rc = self._lib.orc_sample_vertices(self._h, _p(ts, _f64p), int(ts.shape[0]), int(k),
+                                           int(worlds), C.c_uint64(seed), _p(est, _f64p),
+                                           _p(sums, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "sample_vertices")
+        return est, sums
+
+
 def load(n, src, dst, p) -> OracleGraph:
     return OracleGraph(n, src, dst, p)
 
@@ -221,3 +249,7 @@ def philox4x32_10(ctr, key):
 
 def sample_edge(seed, world, i, m) -> int:
     return int(_load().orc_sample_edge(C.c_uint64(seed), C.c_uint32(world), C.c_uint64(i), int(m)))
+
+
+def sample_vertex(seed, world, i, n) -> int:
+    return int(_load().orc_sample_vertex(C.c_uint64(seed), C.c_uint32(world), C.c_uint64(i), int(n)))

@@ -41,6 +41,15 @@
  *    Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with key
  *    (seed_lo ^ w, seed_hi) and counter (i_lo, i_hi, 0, 0); the edge index is the
  *    high 64 bits of (x1:x0) * m.
+ *  - orc_vertex_local: the local count that the vertex-sampling framework (Section
+ *    6.1) needs, taken as its plain definition: every triangle containing the query
+ *    vertex, classified at t. (The improved vertex local search as printed counts
+ *    some triangles twice and misses others; the unbiasedness proof assumes the
+ *    plain count, which is what this computes.)
+ *  - orc_sample_vertices: Algorithm "Baseline Vertex Sampling" (Section 6.1) with
+ *    exactly k uniform draws with replacement; the estimate is n * (sum of local
+ *    counts) / (3k). Vertex draw i of world w is the Philox block of edge draw i of
+ *    world w, mapped to the high 64 bits of (x1:x0) * n.
  */
 #include <math.h>
 #include <stdint.h>
@@ -720,6 +729,95 @@ int orc_sample(const orc_graph* g, const double* t, int nt, int64_t k, int32_t w
             }
             for (int j = 0; j < 2 * nt; j++)
                 est[(size_t)w * nt * 2 + j] = ((double)S[j] * (double)g->m) / (3.0 * (double)k);
+        }
+        free(loc);
+    }
+    free(c);
+    return fail ? ORC_E_NOMEM : ORC_OK;
+}
+
+/* ---------------------------------------------------------------- vertex sampling */
+
+/* Every triangle {q, u, w} with u < w: u a neighbour of q, w a neighbour of u that is
+ * also a neighbour of q. */
+static void vertex_local_one(const orc_graph* g, int32_t q, const double* c, int nt, int64_t* out) {
+    for (int j = 0; j < nt; j++) out[2 * j] = out[2 * j + 1] = 0;
+    for (int64_t a = g->off[q]; a < g->off[q + 1]; a++) {
+        int32_t u = g->nbr[a];
+        for (int64_t b = g->off[u]; b < g->off[u + 1]; b++) {
+            int32_t w = g->nbr[b];
+            if (w <= u || w == q) continue;
+            int32_t eqw = orc_find(g, q, w);
+            if (eqw < 0) continue;
+            double s = orc_s(g->d[g->eid[a]], g->d[g->eid[b]], g->d[eqw]);
+            for (int j = 0; j < nt; j++) {
+                int k = orc_classify(s, c[j]);
+                if (k) out[2 * j + (k - 1)]++;
+            }
+        }
+    }
+}
+
+int orc_vertex_local(const orc_graph* g, const double* t, int nt, const int64_t* vs, int64_t k,
+                     int64_t* out) {
+    if (nt <= 0 || k < 0) return ORC_E_INVALID;
+    for (int64_t i = 0; i < k; i++)
+        if (vs[i] < 0 || vs[i] >= g->n) return ORC_E_INVALID;
+    double* c = (double*)malloc(sizeof(double) * (size_t)nt);
+    if (!c) return ORC_E_NOMEM;
+    for (int j = 0; j < nt; j++) {
+        if (check_t(t[j])) { free(c); return ORC_E_INVALID; }
+        c[j] = orc_c(t[j]);
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < k; i++)
+        vertex_local_one(g, (int32_t)vs[i], c, nt, out + (size_t)i * nt * 2);
+    free(c);
+    return ORC_OK;
+}
+
+/* vertex drawn for sample i of world w (the Philox block of edge draw i of world w) */
+int64_t orc_sample_vertex(uint64_t seed, uint32_t world, uint64_t i, int64_t n) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0u, 0u};
+    uint32_t key[2] = {(uint32_t)seed ^ world, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    uint64_t x64 = ((uint64_t)x[1] << 32) | (uint64_t)x[0];
+    return (int64_t)(((unsigned __int128)x64 * (unsigned __int128)(uint64_t)n) >> 64);
+}
+
+/* Vertex-sampling estimator, replayed draw for draw.
+ * sums[w][j][0/1]: sum of local balanced / unbalanced counts of world w at t_j;
+ * est[w][j][0/1] = (double)sum * (double)n / (3.0 * (double)k). */
+int orc_sample_vertices(const orc_graph* g, const double* t, int nt, int64_t k, int32_t worlds,
+                        uint64_t seed, double* est, int64_t* sums) {
+    if (nt <= 0 || k <= 0 || worlds <= 0 || g->n <= 0) return ORC_E_INVALID;
+    double* c = (double*)malloc(sizeof(double) * (size_t)nt);
+    if (!c) return ORC_E_NOMEM;
+    for (int j = 0; j < nt; j++) {
+        if (check_t(t[j])) { free(c); return ORC_E_INVALID; }
+        c[j] = orc_c(t[j]);
+    }
+    int fail = 0;
+#pragma omp parallel
+    {
+        int64_t* loc = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt * 2);
+        if (!loc) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t w = 0; w < worlds; w++) {
+            if (!loc) continue;
+            int64_t* S = sums + (size_t)w * nt * 2;
+            for (int j = 0; j < 2 * nt; j++) S[j] = 0;
+            for (int64_t i = 0; i < k; i++) {
+                int64_t q = orc_sample_vertex(seed, (uint32_t)w, (uint64_t)i, g->n);
+                vertex_local_one(g, (int32_t)q, c, nt, loc);
+                for (int j = 0; j < 2 * nt; j++) S[j] += loc[j];
+            }
+            for (int j = 0; j < 2 * nt; j++)
+                est[(size_t)w * nt * 2 + j] = ((double)S[j] * (double)g->n) / (3.0 * (double)k);
         }
         free(loc);
     }

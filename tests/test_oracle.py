@@ -365,6 +365,83 @@ def test_sample_edge_is_uniform():
     assert chi2 < 200  # 96 degrees of freedom; p ~ 1e-8 beyond this
 
 
+# ---------------------------------------------------------------- vertex sampling
+
+@pytest.mark.parametrize("gi", range(6))
+def test_vertex_local_matches_bruteforce(gi):
+    """Local counts at every vertex equal the exact rational brute force's triangles
+    through that vertex (definitions taken literally, every vertex triple)."""
+    n, lo, hi = tiny_graphs()[gi]
+    p = inputs.draw_p(lo.shape[0], "dyadic16", 40 + gi)
+    g = load(n, lo, hi, p)
+    loc = g.vertex_local(TS)
+    for j, t in enumerate(TS):
+        bal, unbal = bf.classify_all(n, lo, hi, p, t)
+        want = np.zeros((n, 2), np.int64)
+        for cls, tris in ((0, bal), (1, unbal)):
+            for tri in tris:
+                for v in tri:
+                    want[v, cls] += 1
+        assert np.array_equal(loc[:, j, :], want), (gi, t)
+
+
+def test_vertex_local_sums_and_edge_identity():
+    """Summed over all vertices the local counts are three times the counts (each
+    triangle has three vertices, the identity behind the unbiasedness proof of Section
+    6.1), and each vertex's count is half the sum of the local counts of its edges (a
+    triangle through q has two edges at q)."""
+    n, lo, hi = inputs.chung_lu_graph()
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = load(n, lo, hi, p)
+    ts = [0.5, 0.6, 0.75, 0.9]
+    loc = g.vertex_local(ts)
+    tot = loc.sum(axis=0)
+    for j, t in enumerate(ts):
+        nb, nu = g.count(t)
+        assert tot[j, 0] == 3 * nb and tot[j, 1] == 3 * nu
+    el = g.edge_local(ts)
+    lo2, hi2, _ = g.edges()
+    at = np.zeros((n, len(ts), 2), np.int64)
+    np.add.at(at, lo2, el)
+    np.add.at(at, hi2, el)
+    assert np.all(at % 2 == 0) and np.array_equal(at // 2, loc)
+
+
+def test_vertex_sampler_replay_and_unbiased():
+    n, lo, hi = inputs.chung_lu_graph()
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = load(n, lo, hi, p)
+    ts = [0.6, 0.8]
+    k, W, seed = 100, 256, 0xBADC0FFEE
+    est, sums = g.sample_vertices(ts, k, W, seed)
+    for w in (0, 200):
+        vs = np.array([oracle.sample_vertex(seed, w, i, g.n) for i in range(k)], np.int64)
+        loc = g.vertex_local(ts, vs)
+        assert np.array_equal(loc.sum(axis=0), sums[w])
+        for j in range(len(ts)):
+            for q in range(2):
+                assert est[w, j, q] == (float(sums[w, j, q]) * float(g.n)) / (3.0 * float(k))
+    exact = np.array([g.count(t) for t in ts], dtype=np.float64)
+    mean = est.mean(axis=0)
+    se = est.std(axis=0, ddof=1) / np.sqrt(W)
+    assert np.all(np.abs(mean - exact) <= 4 * se + 1e-9), (mean, exact, se)
+
+
+def test_sample_vertex_convention():
+    """Vertex draw i of world w uses the Philox block of edge draw i of world w and maps
+    it to the high word of (x1:x0) * n."""
+    for seed, w, i, n in [(0x0123456789ABCDEF, 0, 0, 2000), (5, 1023, 2 ** 33 + 7, 1048576),
+                          (2 ** 64 - 1, 77, 999, 3)]:
+        x = oracle.philox4x32_10([i & 0xFFFFFFFF, i >> 32, 0, 0],
+                                 [(seed & 0xFFFFFFFF) ^ w, seed >> 32])
+        x64 = (int(x[1]) << 32) | int(x[0])
+        assert oracle.sample_vertex(seed, w, i, n) == (x64 * n) >> 64
+    draws = np.array([oracle.sample_vertex(11, 2, i, 61) for i in range(12000)])
+    assert draws.min() >= 0 and draws.max() < 61
+    cnt = np.bincount(draws, minlength=61)
+    assert ((cnt - 12000 / 61) ** 2 / (12000 / 61)).sum() < 140  # 60 dof
+
+
 ROCRAND_SRC = r"""
 #include <rocrand/rocrand_philox4x32_10.h>
 #include <cstdio>
