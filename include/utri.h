@@ -66,8 +66,8 @@ enum { UTRI_BAL = 1, UTRI_UNBAL = 2, UTRI_BOTH = 3 };
 /* Pointer kinds for inputs / outputs that may live on either side. */
 enum { UTRI_HOST_PTR = 0, UTRI_DEVICE_PTR = 1 };
 
-/* Sampling schemes. */
-enum { UTRI_SAMPLE_EDGE = 0 };
+/* Sampling schemes: edge sampling (Section 6.2) and vertex sampling (Section 6.1). */
+enum { UTRI_SAMPLE_EDGE = 0, UTRI_SAMPLE_VERTEX = 1 };
 
 /*
  * Build a graph handle (Definition "Uncertain Signed Graph", Section 3).
@@ -154,12 +154,29 @@ int utri_edge_local(utri_graph* g, const double* t, int nt, const int64_t* eids,
                     int64_t* out, void* hip_stream);
 
 /*
- * Edge-sampling estimator (Algorithm "Baseline Edge Sampling" with the improved local
- * search, Section 6.2), `worlds` independent replicates of k draws each. Draw i of
- * replicate w is Philox4x32-10 (Salmon et al., SC'11) with key (seed_lo ^ w, seed_hi)
- * and counter (i_lo, i_hi, 0, 0); the edge is the high 64 bits of (x1:x0) * m.
- * est: device FP64 [worlds][nt][2] = m * (sum of local counts) / (3k), computed as
- * ((double)sum * (double)m) / (3.0 * (double)k). scheme must be UTRI_SAMPLE_EDGE.
+ * Local counts of the vertex-sampling framework (Algorithm "Baseline Vertex Sampling",
+ * Section 6.1): for each listed vertex, every uncertain balanced / unbalanced triangle
+ * containing it, at each threshold (the plain local count that the framework's
+ * unbiasedness proof assumes; the improved vertex local search as printed counts some
+ * triangles twice and misses others). vids: device int64 [k], original vertex ids in
+ * [0, n) (UTRI_E_INVALID otherwise); out: device int64 [k][nt][2]; 1 <= nt <= 64.
+ */
+int utri_vertex_local(utri_graph* g, const double* t, int nt, const int64_t* vids, int64_t k,
+                      int64_t* out, void* hip_stream);
+
+/*
+ * Sampling estimators, `worlds` independent replicates of k uniform draws (with
+ * replacement) each. Draw i of replicate w is Philox4x32-10 (Salmon et al., SC'11) with
+ * key (seed_lo ^ w, seed_hi) and counter (i_lo, i_hi, 0, 0), mapped to the high 64 bits
+ * of (x1:x0) * range.
+ *  - UTRI_SAMPLE_EDGE (Algorithm "Baseline Edge Sampling" with the improved local
+ *    search, Section 6.2): range m, est = m * (sum of edge local counts) / (3k);
+ *  - UTRI_SAMPLE_VERTEX (Algorithm "Baseline Vertex Sampling", Section 6.1, with the
+ *    plain vertex local count of utri_vertex_local): range n, est = n * (sum of vertex
+ *    local counts) / (3k). Needs one host synchronisation to size its edge records.
+ * est: device FP64 [worlds][nt][2], computed as ((double)sum * (double)range) /
+ * (3.0 * (double)k). Errors: UTRI_E_INVALID for another scheme, k <= 0, worlds <= 0, or
+ * an empty range (m = 0 for edges, n = 0 for vertices).
  */
 int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
                 int scheme, double* est, void* hip_stream);

@@ -178,11 +178,11 @@ int count_impl(utri_graph* g, double t, int method, int64_t out[2], hipStream_t 
 // Launch sequence of the batch path (also what gets captured into a hipGraph).
 int64_t n_draws(const SampleParams& sp) { return (int64_t)sp.worlds * sp.k; }
 
-// Grouped sampling of draws [t_begin, worlds * k), one pass of g->sample_pass at a time.
+// Grouped sampling of draws [t_begin, t_end), one pass of g->sample_pass at a time.
 int sample_passes(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t_begin,
-                  hipStream_t s) {
-    for (int64_t t0 = t_begin; t0 < n_draws(sp); t0 += g->sample_pass) {
-        UTRI_TRY(utri_sample_prepare(g, sp, slen, t0, std::min<int64_t>(n_draws(sp), t0 + g->sample_pass), s));
+                  int64_t t_end, hipStream_t s) {
+    for (int64_t t0 = t_begin; t0 < t_end; t0 += g->sample_pass) {
+        UTRI_TRY(utri_sample_prepare(g, sp, slen, t0, std::min<int64_t>(t_end, t0 + g->sample_pass), s));
         UTRI_TRY(utri_sample_launch(g, sp, slen, s));
     }
     return UTRI_OK;
@@ -228,7 +228,7 @@ int batch_sequence(utri_graph* g, const double* dc, const int32_t* dord, int nt,
     }
     UTRI_TRY(utri_batch_launch(g, wp, items, nitems, len, 0, sp, slen, s));
     // draws beyond the first pass in further launches
-    if (sp.hist) UTRI_TRY(sample_passes(g, sp, slen, g->sample_pass, s));
+    if (sp.hist) UTRI_TRY(sample_passes(g, sp, slen, g->sample_pass, n_draws(sp), s));
     if (exact) UTRI_TRY(utri_finalize_launch((const unsigned long long*)hw, 1, nt, dord, g->m, 1, exact, nullptr, s));
     if (sp.hist) UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k, nullptr, est, s));
     return UTRI_OK;
@@ -491,11 +491,37 @@ int utri_edge_local(utri_graph* g, const double* t, int nt, const int64_t* eids,
     return UTRI_OK;
 }
 
+int utri_vertex_local(utri_graph* g, const double* t, int nt, const int64_t* vids, int64_t k,
+                      int64_t* out, void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (k < 0 || (k > 0 && (!vids || !out))) return UTRI_E_INVALID;
+    std::vector<double> cv;
+    std::vector<int32_t> order;
+    UTRI_TRY(sort_thresholds(t, nt, cv, order));
+    if (k == 0) return UTRI_OK;
+    hipStream_t s = as_stream(hip_stream);
+    // vertex ids come from the caller: check the range before any kernel indexes with them
+    UTRI_HIP_TRY(hipMemsetAsync(g->d_flags, 0, sizeof(uint32_t), s));
+    hipLaunchKernelGGL(k_check_eids, dim3(nblk(k)), dim3(256), 0, s, vids, k, g->n, g->d_flags);
+    UTRI_HIP_TRY(hipGetLastError());
+    uint32_t bad = 0;
+    UTRI_HIP_TRY(hipMemcpyAsync(&bad, g->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return UTRI_E_INVALID;
+    double* dc;
+    int32_t* dord;
+    UTRI_TRY(upload_thresholds(g, cv, order, s, &dc, &dord));
+    UTRI_TRY(utri_vertex_local_launch(g, dc, dord, nt, vids, k, out, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    return UTRI_OK;
+}
+
 int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
                 int scheme, double* est, void* hip_stream) {
     UTRI_TRY(check_graph(g));
-    if (scheme != UTRI_SAMPLE_EDGE || k <= 0 || worlds <= 0 || !est) return UTRI_E_INVALID;
-    if (g->m == 0) return UTRI_E_INVALID;
+    if ((scheme != UTRI_SAMPLE_EDGE && scheme != UTRI_SAMPLE_VERTEX) || k <= 0 || worlds <= 0 || !est)
+        return UTRI_E_INVALID;
+    if (scheme == UTRI_SAMPLE_EDGE ? g->m == 0 : g->n == 0) return UTRI_E_INVALID;
     std::vector<double> cv;
     std::vector<int32_t> order;
     UTRI_TRY(sort_thresholds(t, nt, cv, order));
@@ -518,9 +544,19 @@ int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t world
     sp.worlds = worlds;
     sp.chunk = g->sample_chunk;
     sp.hist = (unsigned long long*)hs;
-    UTRI_TRY(sample_passes(g, sp, slen, 0, s));
-    UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k,
-                                  nullptr, est, s));
+    if (scheme == UTRI_SAMPLE_EDGE) {
+        UTRI_TRY(sample_passes(g, sp, slen, 0, n_draws(sp), s));
+        UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->m, k,
+                                      nullptr, est, s));
+    } else {
+        // every sampled vertex becomes the edge records of its prefix; each triangle at
+        // the vertex is counted through both of its edges there, hence the halving
+        int64_t R = 0;
+        UTRI_TRY(utri_vertex_prepare(g, sp, slen, s, &R));
+        if (g->m > 0) UTRI_TRY(sample_passes(g, sp, slen, 0, R, s));
+        UTRI_TRY(utri_finalize_launch((const unsigned long long*)hs, worlds, nt, dord, g->n, k,
+                                      nullptr, est, s, 2));
+    }
     UTRI_HIP_TRY(hipStreamSynchronize(s));
     return UTRI_OK;
 }

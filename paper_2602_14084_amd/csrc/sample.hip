@@ -1,5 +1,6 @@
 // sample.hip -- edge-sampling estimator (Algorithms "Baseline Edge Sampling" and
-// "Improved Edge Local Search", Section 6.2), per-edge local counts, and the
+// "Improved Edge Local Search", Section 6.2), the vertex-sampling estimator (Algorithm
+// "Baseline Vertex Sampling", Section 6.1), per-edge and per-vertex local counts, and the
 // histogram-to-count / estimate finalisation shared with the batch path.
 //
 // Local search of a sampled edge e = (a, b): nothing if |d_e| < c (Lemma 2); else the
@@ -8,6 +9,13 @@
 // cost is the pruned degree of the cheaper endpoint (Theorem 6.3). The estimator groups a
 // pass of draws by the looked-up endpoint first (counting sort: count, scan, scatter) so a
 // group's row is staged once (walk_common.h).
+//
+// Vertex sampling reuses that machinery: the local count at a sampled vertex q is every
+// triangle containing q (the plain count its unbiasedness proof assumes), and each such
+// triangle {q, u, w} is found exactly twice among the edge local counts of q's edges,
+// through (q, u) and through (q, w). So a sampled vertex becomes the edge records of its
+// Lemma-2 prefix (edges with |d| < c close no classified triangle), the records go through
+// the grouped edge sampler, and the world's histogram is halved exactly at the end.
 #include <algorithm>
 
 #include "walk_common.h"
@@ -40,10 +48,16 @@ __global__ void k_symlen(const int64_t* __restrict__ off, const double* __restri
 __device__ __forceinline__ bool pass_draw(const SampleParams& sp, const SampleGraph& G,
                                           const int32_t* __restrict__ slen, int64_t t, int64_t& e,
                                           int32_t& world, int32_t& y) {
-    const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
-    world = (int32_t)(t / sp.k);
-    const int64_t i = t - (int64_t)world * sp.k;
-    e = utri_sample_edge(seed, (uint32_t)world, (uint64_t)i, G.m);
+    if (sp.vrec) {
+        const int64_t r = sp.vrec[t];
+        e = r & 0xFFFFFFFFll;
+        world = (int32_t)(r >> 32);
+    } else {
+        const uint64_t seed = sp.seed_dev ? *sp.seed_dev : sp.seed;
+        world = (int32_t)(t / sp.k);
+        const int64_t i = t - (int64_t)world * sp.k;
+        e = utri_sample_edge(seed, (uint32_t)world, (uint64_t)i, G.m);
+    }
     if (fabs(G.e_d[e]) < sp.cmin) return false;
     int32_t x;
     int lx;
@@ -152,10 +166,94 @@ __global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double*
     }
 }
 
+// Vertex draw t = world * k + i: the sampled vertex (new id) and its prefix length.
+__global__ void k_v_draw(uint64_t seed, int64_t k, int64_t T, int64_t n,
+                         const int32_t* __restrict__ inv, const int32_t* __restrict__ slen,
+                         int32_t* __restrict__ vq, int32_t* __restrict__ vlen) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int32_t world = (int32_t)(t / k);
+    const int64_t i = t - (int64_t)world * k;
+    const int32_t q = inv[utri_sample_vertex(seed, (uint32_t)world, (uint64_t)i, n)];
+    vq[t] = q;
+    vlen[t] = slen[q];
+}
+
+// One wave per vertex draw writes the edge records of the vertex's prefix.
+__global__ void __launch_bounds__(TPB) k_v_expand(const int32_t* __restrict__ vq,
+                                                  const int32_t* __restrict__ vlen,
+                                                  const int64_t* __restrict__ voff, int64_t T,
+                                                  int64_t k, const int64_t* __restrict__ s_off,
+                                                  const int32_t* __restrict__ s_eid,
+                                                  int64_t* __restrict__ vrec) {
+    const int64_t W = (int64_t)gridDim.x * WPB;
+    for (int64_t t = (int64_t)blockIdx.x * WPB + threadIdx.x / UTRI_WAVE; t < T; t += W) {
+        const int64_t base = s_off[vq[t]], o = voff[t];
+        const int64_t wtag = (t / k) << 32;
+        const int L = vlen[t];
+        for (int j = utri_lane(); j < L; j += UTRI_WAVE) vrec[o + j] = (int64_t)s_eid[base + j] | wtag;
+    }
+}
+
+// One wave per listed vertex q (new id): the edge local counts of every edge (q, u) of
+// q's prefix at the smallest threshold, summed in LDS; out = half the sums (each
+// triangle at q is found through both of its edges at q).
+__global__ void __launch_bounds__(TPB) k_vertex_local(SampleGraph G, const int32_t* __restrict__ slen,
+                                                      const double* __restrict__ cv,
+                                                      const int32_t* __restrict__ order, int nt,
+                                                      const int64_t* __restrict__ vids, int64_t k,
+                                                      int64_t* __restrict__ out) {
+    __shared__ unsigned long long hist[WPB][2][NB];
+    const int wib = threadIdx.x / UTRI_WAVE;
+    const int lane = utri_lane();
+    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
+    const int64_t W = (int64_t)gridDim.x * WPB;
+    thresh_stage(cv, nt);
+    for (int64_t qi = gw; qi < k; qi += W) {
+        for (int t = lane; t < 2 * NB; t += UTRI_WAVE) hist[wib][t / NB][t % NB] = 0;
+        utri_wave_sync();
+        const int32_t q = G.inv[vids[qi]];
+        const int64_t qoff = G.s_off[q];
+        const int lq = slen[q];
+        for (int a = 0; a < lq; a++) {
+            const int32_t u = G.s_adj[qoff + a];
+            const double de = G.s_d[qoff + a];
+            const int lu = slen[u];
+            // stream the shorter prefix, look its entries up in the other row's table
+            const bool qx = (lq < lu) || (lq == lu && q < u);
+            const int32_t y = qx ? u : q;
+            const int64_t xoff = G.s_off[qx ? q : u];
+            const int lx = qx ? lq : lu;
+            const int64_t hoff = G.h_off[y];
+            const int lg = hbuckets_lg(G, y);
+            for (int j = lane; j < lx; j += UTRI_WAVE) {
+                const int64_t sl = sym_lookup(G.h_key, hoff, lg, G.s_adj[xoff + j]);
+                if (sl >= 0) {
+                    const double s = utri_tri_s(de, G.s_d[xoff + j], G.h_d[sl]);
+                    bool bal;
+                    const int bin = thresh_bin(s, bal);
+                    if (bin > 0) atomicAdd(&hist[wib][bal ? 0 : 1][bin], 1ull);
+                }
+            }
+        }
+        utri_wave_sync();
+        for (int js = lane; js < nt; js += UTRI_WAVE) {
+            unsigned long long cb = 0, cu = 0;
+            for (int bin = js + 1; bin <= nt; bin++) { cb += hist[wib][0][bin]; cu += hist[wib][1][bin]; }
+            const int jo = order[js];
+            out[(qi * nt + jo) * 2] = (int64_t)(cb / 2);
+            out[(qi * nt + jo) * 2 + 1] = (int64_t)(cu / 2);
+        }
+        utri_wave_sync();
+    }
+}
+
 // hist [rows][2][nt+1] -> counts [rows][nt][2] (threshold order given by `order`) and
-// est [rows][nt][2] = ((double)count * (double)m) / (3.0 * (double)k)
+// est [rows][nt][2] = ((double)count * (double)num) / (3.0 * (double)k), where count is
+// the suffix sum of the bins divided by div (2 for vertex sampling, exact: every triangle
+// is counted twice there).
 __global__ void k_finalize(const unsigned long long* __restrict__ hist, int rows, int nt,
-                           const int32_t* __restrict__ order, int64_t m, int64_t k,
+                           const int32_t* __restrict__ order, int64_t m, int64_t k, int div,
                            int64_t* __restrict__ counts, double* __restrict__ est) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)rows * nt * 2) return;
@@ -165,6 +263,7 @@ __global__ void k_finalize(const unsigned long long* __restrict__ hist, int rows
     const unsigned long long* h = hist + (r * 2 + cls) * (nt + 1);
     unsigned long long c = 0;
     for (int bin = js + 1; bin <= nt; bin++) c += h[bin];
+    c /= (unsigned long long)div;
     const int jo = order ? order[js] : js;
     const int64_t o = (r * nt + jo) * 2 + cls;
     if (counts) counts[o] = (int64_t)c;
@@ -270,11 +369,56 @@ int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* or
 
 int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const int32_t* order,
                          int64_t m, int64_t k, int64_t* counts_out, double* est_out,
-                         hipStream_t s) {
+                         hipStream_t s, int div) {
     const int64_t tot = (int64_t)rows * nt * 2;
     if (tot == 0) return UTRI_OK;
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(tot)), dim3(TPB), 0, s, hist, rows, nt, order,
-                       m, k > 0 ? k : 1, counts_out, est_out);
+                       m, k > 0 ? k : 1, div, counts_out, est_out);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+int utri_vertex_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, hipStream_t s,
+                        int64_t* n_records) {
+    const int64_t T = (int64_t)sp.worlds * sp.k;
+    void *pq, *pl, *po, *pr;
+    UTRI_TRY(utri_scratch(g, SCR_VQ, sizeof(int32_t) * (size_t)T, &pq));
+    UTRI_TRY(utri_scratch(g, SCR_VLEN, sizeof(int32_t) * (size_t)T, &pl));
+    UTRI_TRY(utri_scratch(g, SCR_VOFF, sizeof(int64_t) * (size_t)(T + 1), &po));
+    int32_t* vq = (int32_t*)pq;
+    int32_t* vlen = (int32_t*)pl;
+    int64_t* voff = (int64_t*)po;
+    hipLaunchKernelGGL(k_v_draw, dim3(blocks_for(T)), dim3(TPB), 0, s, sp.seed, sp.k, T, g->n,
+                       (const int32_t*)g->inv, slen, vq, vlen);
+    UTRI_HIP_TRY(hipGetLastError());
+    UTRI_TRY(utri_scan_i32(g, vlen, voff, T, voff + T, s));
+    int64_t R = 0;
+    UTRI_HIP_TRY(hipMemcpyAsync(&R, voff + T, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    UTRI_TRY(utri_scratch(g, SCR_VREC, sizeof(int64_t) * (size_t)(R + 1), &pr));
+    if (R > 0) {
+        const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * 16, (T + WPB - 1) / WPB);
+        hipLaunchKernelGGL(k_v_expand, dim3(blocks), dim3(TPB), 0, s, (const int32_t*)vq,
+                           (const int32_t*)vlen, (const int64_t*)voff, T, sp.k,
+                           (const int64_t*)g->s_off, (const int32_t*)g->s_eid, (int64_t*)pr);
+        UTRI_HIP_TRY(hipGetLastError());
+    }
+    sp.vrec = (const int64_t*)pr;
+    *n_records = R;
+    return UTRI_OK;
+}
+
+int utri_vertex_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
+                             const int64_t* vids, int64_t k, int64_t* out, hipStream_t s) {
+    if (k <= 0) return UTRI_OK;
+    int32_t* slen;
+    double cmin = 0.0;
+    UTRI_HIP_TRY(hipMemcpyAsync(&cmin, cvals, sizeof(double), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    UTRI_TRY(utri_sym_prepare(g, cmin, s, &slen));
+    const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * 8, (k + WPB - 1) / WPB);
+    hipLaunchKernelGGL(k_vertex_local, dim3(blocks), dim3(TPB), 0, s, sample_graph(g),
+                       (const int32_t*)slen, cvals, order, nt, vids, k, out);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

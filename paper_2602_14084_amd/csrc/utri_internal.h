@@ -89,10 +89,14 @@ enum UtriScratch {
     SCR_SCNT,         // int32 [n+2] sampler draws per probed endpoint
     SCR_SOFF,         // int64 [n+1] sampler group offsets
     SCR_SREC,         // int64 sampler draw records of one pass
-    SCR_SICNT,        // int32 [2n] sampler items per group (work-group, wave)
-    SCR_SIOFF,        // int64 [2n] sampler item offsets
+    SCR_SICNT,        // int32 [3n] sampler items per group (work-group, wave, hub)
+    SCR_SIOFF,        // int64 [3n] sampler item offsets
     SCR_SITEMS,       // int64 sampler items
-    SCR_SQ,           // int64 [8] sampler item counts and work-queue counters
+    SCR_SQ,           // int64 [16] sampler item counts and work-queue counters
+    SCR_VQ,           // int32 [worlds * k] sampled vertices (new ids)
+    SCR_VLEN,         // int32 [worlds * k] their Lemma-2 prefix lengths
+    SCR_VOFF,         // int64 [worlds * k + 1] offsets of their edge records
+    SCR_VREC,         // int64 edge records of the sampled vertices: edge | world << 32
     SCR_COUNT
 };
 
@@ -315,13 +319,22 @@ __device__ inline void utri_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-// edge drawn by sample i of world w
-__device__ inline int64_t utri_sample_edge(uint64_t seed, uint32_t world, uint64_t i, int64_t m) {
+// index in [0, range) drawn by sample i of world w: the high 64 bits of (x1:x0) * range
+// for the Philox block with counter (i_lo, i_hi, 0, 0) and key (seed_lo ^ w, seed_hi)
+__device__ inline int64_t utri_draw_index(uint64_t seed, uint32_t world, uint64_t i, int64_t range) {
     uint32_t x[4];
     utri_philox((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u, (uint32_t)seed ^ world,
                 (uint32_t)(seed >> 32), x);
     uint64_t x64 = ((uint64_t)x[1] << 32) | (uint64_t)x[0];
-    return (int64_t)__umul64hi(x64, (uint64_t)m);
+    return (int64_t)__umul64hi(x64, (uint64_t)range);
+}
+
+// edge drawn by sample i of world w (edge sampling) and vertex (vertex sampling)
+__device__ inline int64_t utri_sample_edge(uint64_t seed, uint32_t world, uint64_t i, int64_t m) {
+    return utri_draw_index(seed, world, i, m);
+}
+__device__ inline int64_t utri_sample_vertex(uint64_t seed, uint32_t world, uint64_t i, int64_t n) {
+    return utri_draw_index(seed, world, i, n);
 }
 
 // ------------------------------------------------------------------ kernels (host launchers)
@@ -377,6 +390,9 @@ struct SampleParams {
     int32_t worlds = 0;
     int chunk = 128;                // draws per group item
     unsigned long long* hist = nullptr;  // [worlds][2][nt+1]
+    // vertex sampling: draw t is the edge record vrec[t] (edge | world << 32) of a sampled
+    // vertex's prefix instead of a Philox-drawn edge
+    const int64_t* vrec = nullptr;
     // draws of one pass grouped by the probed endpoint (set by utri_sample_prepare)
     int64_t t0 = 0, t1 = 0;              // flat draw range [t0, t1), t = world * k + i
     const int64_t* rec = nullptr;        // edge | world << 32, grouped by probed endpoint
@@ -393,12 +409,18 @@ int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen
 int utri_sample_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t0,
                         int64_t t1, hipStream_t s);
 int utri_sample_launch(utri_graph* g, const SampleParams& sp, const int32_t* slen, hipStream_t s);
+// Vertex sampling: draw the worlds * k vertices, expand each into the edge records of its
+// Lemma-2 prefix (sp.vrec) and return their number (one host synchronisation).
+int utri_vertex_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, hipStream_t s,
+                        int64_t* n_records);
+int utri_vertex_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
+                             const int64_t* vids, int64_t k, int64_t* out, hipStream_t s);
 int utri_batch_launch(utri_graph* g, const WalkParams& wp, const int64_t* items,
                       const int64_t* n_items_dev, const int32_t* len, int64_t n_items_bound,
                       const SampleParams& sp, const int32_t* slen, hipStream_t s);
 int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const int32_t* order,
                          int64_t m, int64_t k, int64_t* counts_out, double* est_out,
-                         hipStream_t s);
+                         hipStream_t s, int div = 1);
 int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
                            const int64_t* eids, int64_t k, int64_t* out, hipStream_t s);
 int64_t utri_walk_items_bound(utri_graph* g);

@@ -29,12 +29,12 @@ UTRI_E_RANGE = -6
 UTRI_PLAIN, UTRI_PRUNED, UTRI_PRUNED_L3 = 0, 1, 2
 UTRI_BAL, UTRI_UNBAL, UTRI_BOTH = 1, 2, 3
 UTRI_HOST_PTR, UTRI_DEVICE_PTR = 0, 1
-UTRI_SAMPLE_EDGE = 0
+UTRI_SAMPLE_EDGE, UTRI_SAMPLE_VERTEX = 0, 1
 
 ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
-    "utri_expected_grad", "utri_edge_local", "utri_sample", "utri_batch", "utri_autotune",
+    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_sample", "utri_batch", "utri_autotune",
     "utri_walk_stats", "utri_timing", "utri_strerror",
 ]
 
@@ -69,6 +69,7 @@ def lib():
     L.utri_expected.argtypes = [vp, P(f64), vp]
     L.utri_expected_grad.argtypes = [vp, vp, vp]
     L.utri_edge_local.argtypes = [vp, P(f64), C.c_int, vp, i64, vp, vp]
+    L.utri_vertex_local.argtypes = [vp, P(f64), C.c_int, vp, i64, vp, vp]
     L.utri_sample.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, C.c_int, vp, vp]
     L.utri_batch.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, vp, vp, C.c_int, vp]
     L.utri_autotune.argtypes = [vp, f64, C.c_char_p, vp]
@@ -225,12 +226,23 @@ def utri_edge_local(h, ts, eids, stream=None):
     return out
 
 
-def utri_sample(h, ts, k, worlds, seed, stream=None):
+def utri_vertex_local(h, ts, vids, stream=None):
+    torch = _torch()
+    a, pa = _f64_array(ts)
+    v = torch.as_tensor(vids, dtype=torch.int64).to("cuda").contiguous()
+    out = torch.zeros((v.shape[0], a.shape[0], 2), dtype=torch.int64, device="cuda")
+    rc = lib().utri_vertex_local(h, pa, int(a.shape[0]), C.c_void_p(v.data_ptr()),
+                                 int(v.shape[0]), C.c_void_p(out.data_ptr()), _stream(stream))
+    _check(rc, "utri_vertex_local")
+    return out
+
+
+def utri_sample(h, ts, k, worlds, seed, scheme=UTRI_SAMPLE_EDGE, stream=None):
     torch = _torch()
     a, pa = _f64_array(ts)
     est = torch.empty((int(worlds), a.shape[0], 2), dtype=torch.float64, device="cuda")
     rc = lib().utri_sample(h, pa, int(a.shape[0]), int(k), int(worlds), C.c_uint64(seed),
-                           UTRI_SAMPLE_EDGE, C.c_void_p(est.data_ptr()), _stream(stream))
+                           int(scheme), C.c_void_p(est.data_ptr()), _stream(stream))
     _check(rc, "utri_sample")
     return est
 
@@ -330,8 +342,11 @@ class Graph:
     def edge_local(self, ts, eids):
         return utri_edge_local(self._h, ts, eids)
 
-    def sample(self, ts, k, worlds, seed):
-        return utri_sample(self._h, ts, k, worlds, seed)
+    def vertex_local(self, ts, vids):
+        return utri_vertex_local(self._h, ts, vids)
+
+    def sample(self, ts, k, worlds, seed, scheme=UTRI_SAMPLE_EDGE):
+        return utri_sample(self._h, ts, k, worlds, seed, scheme)
 
     def batch(self, ts, k, worlds, seed, use_graph=True, **kw):
         return utri_batch(self._h, ts, k, worlds, seed, use_graph, **kw)

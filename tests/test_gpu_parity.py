@@ -264,6 +264,68 @@ def test_sampler_groups_and_passes(monkeypatch):
     assert np.array_equal(ex.cpu().numpy(), og.count_multi(ts))
 
 
+@pytest.mark.parametrize("ci", [1, 4, 5, 6])
+def test_vertex_local_matches_oracle(ci):
+    name, n, lo, hi = CASES[ci]
+    p = inputs.draw_p(lo.shape[0], "uniform", 51 + ci)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    vids = np.arange(n, dtype=np.int64) if n <= 2000 else \
+        np.random.default_rng(ci).integers(0, n, 1500)
+    ts = [0.8, 0.5, 0.6, 0.9375]
+    say("vertex_local", name, n)
+    got = g.vertex_local(ts, vids).cpu().numpy()
+    assert np.array_equal(got, og.vertex_local(ts, vids)), name
+
+
+def test_vertex_sampler_replays_oracle_exactly():
+    for name, n, lo, hi in [CASES[4], CASES[5], ("rmat12",) + inputs.rmat_graph(12, seed=3)]:
+        p = inputs.draw_p(lo.shape[0], "uniform", 43)
+        og = oracle.load(n, lo, hi, p)
+        g = gpu_graph(n, lo, hi, p)
+        for ts, k, W, seed in [([0.6], 97, 5, 3), ([0.8, 0.5, 0.7], 400, 33, 0xFEEDF00D1234)]:
+            say("sample vertex", name, ts, k, W)
+            est = g.sample(ts, k, W, seed, utri.UTRI_SAMPLE_VERTEX).cpu().numpy()
+            oest, _ = og.sample_vertices(ts, k, W, seed)
+            assert np.array_equal(est, oest), (name, ts)
+
+
+def test_vertex_sampler_groups_and_passes(monkeypatch):
+    # hub vertices expand into thousands of edge records; the records are then cut into
+    # passes of 1,000
+    n, lo, hi = inputs.rmat_graph(15, seed=3)
+    p = inputs.draw_p(lo.shape[0], "uniform", 49)
+    og = oracle.load(n, lo, hi, p)
+    ts, k, W, seed = [0.55, 0.7], 300, 6, 1234
+    want, _ = og.sample_vertices(ts, k, W, seed)
+    say("sample vertex rmat15")
+    g = gpu_graph(n, lo, hi, p)
+    assert np.array_equal(g.sample(ts, k, W, seed, utri.UTRI_SAMPLE_VERTEX).cpu().numpy(), want)
+    monkeypatch.setenv("UTRI_SAMPLE_PASS", "1000")
+    g2 = gpu_graph(n, lo, hi, p)
+    say("sample vertex passes rmat15")
+    assert np.array_equal(g2.sample(ts, k, W, seed, utri.UTRI_SAMPLE_VERTEX).cpu().numpy(), want)
+
+
+def test_vertex_sampler_edge_cases():
+    # a graph with edges but no triangle, and one with isolated vertices only
+    lo = np.array([0, 1, 2], np.int64)
+    hi = np.array([1, 2, 3], np.int64)
+    g = gpu_graph(6, lo, hi, np.array([0.9, 0.1, 0.95]))
+    est = g.sample([0.6], 50, 4, 5, utri.UTRI_SAMPLE_VERTEX).cpu().numpy()
+    assert np.all(est == 0.0)
+    e = gpu_graph(4, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0))
+    assert np.all(e.sample([0.6], 10, 2, 5, utri.UTRI_SAMPLE_VERTEX).cpu().numpy() == 0.0)
+    with pytest.raises(utri.UtriError) as ei:
+        g.vertex_local([0.6], np.array([0, 6], np.int64))
+    assert ei.value.code == utri.UTRI_E_INVALID
+    for bad in [(0, 4, utri.UTRI_SAMPLE_VERTEX), (10, 0, utri.UTRI_SAMPLE_VERTEX), (10, 4, 7)]:
+        with pytest.raises(utri.UtriError) as ei:
+            g.sample([0.6], bad[0], bad[1], 5, bad[2])
+        assert ei.value.code == utri.UTRI_E_INVALID
+    assert g.vertex_local([0.6], np.zeros(0, np.int64)).shape == (0, 1, 2)
+
+
 def test_batch_eager_and_graph_replays():
     n, lo, hi = inputs.rmat_graph(13, seed=9)
     p = inputs.draw_p(lo.shape[0], "beta22", 2)
