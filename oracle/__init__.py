@@ -55,6 +55,7 @@ def _load():
     lib.orc_sample_vertex.restype = C.c_int64
     lib.orc_sample_vertices.argtypes = [vp, _f64p, C.c_int, C.c_int64, C.c_int32, C.c_uint64,
                                         _f64p, _i64p]
+    lib.orc_topk.argtypes = [vp, C.c_int64, C.c_int, _i32p, _f64p, _i64p]
     lib.orc_num_threads.restype = C.c_int
     _lib = lib
     return lib
@@ -232,6 +233,21 @@ class OracleGraph:
         if rc != OK:
             raise OracleError(rc, "sample_vertices")
         return est, sums
+
+
+    def topk(self, k, which):
+        """(triples [r][3] int32 sorted within, s [r] f64), r = min(k, #qualifying); which is
+        1 for the most balanced (smallest s, s <= 0) or 2 for the most unbalanced (largest
+        s, s > 0); ties in s by the triple, lexicographically."""
+        tri = np.zeros((max(k, 1), 3), np.int32)
+        sv = np.zeros(max(k, 1), np.float64)
+        cnt = np.zeros(1, np.int64)
+        rc = self._lib.orc_topk(self._h, int(k), int(which), _p(tri, _i32p), _p(sv, _f64p),
+                                _p(cnt, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "topk")
+        r = int(cnt[0])
+        return tri[:r].copy(), sv[:r].copy()
 
 
 def load(n, src, dst, p) -> OracleGraph:

@@ -46,6 +46,11 @@
  *    vertex, classified at t. (The improved vertex local search as printed counts
  *    some triangles twice and misses others; the unbiasedness proof assumes the
  *    plain count, which is what this computes.)
+ *  - orc_topk: the top-k search of Section 5 ("Adaption to Top-k Search"), taken as
+ *    its plain result: among the uncertain balanced triangles at t = 1/2 (P_bal >= 1/2,
+ *    s <= 0) the k with the highest P_bal, i.e. the smallest s; among the unbalanced ones
+ *    (P_unbal > 1/2, s > 0) the k with the largest s. Ties in s are broken by the sorted
+ *    id triple, lexicographically; fewer than k qualifying triangles give all of them.
  *  - orc_sample_vertices: Algorithm "Baseline Vertex Sampling" (Section 6.1) with
  *    exactly k uniform draws with replacement; the estimate is n * (sum of local
  *    counts) / (3k). Vertex draw i of world w is the Philox block of edge draw i of
@@ -823,4 +828,96 @@ int orc_sample_vertices(const orc_graph* g, const double* t, int nt, int64_t k, 
     }
     free(c);
     return fail ? ORC_E_NOMEM : ORC_OK;
+}
+
+/* ---------------------------------------------------------------- top-k */
+
+typedef struct { double s; int32_t a, b, c; } orc_st;
+typedef struct { orc_st* buf; int64_t len, cap; } orc_stvec;
+
+typedef struct {
+    const orc_graph* g;
+    int cls;          /* 1 balanced, 2 unbalanced */
+    orc_stvec* v;     /* [threads] */
+    int* fail;        /* [threads] */
+} topk_ctx;
+
+static void topk_visit(void* vctx, int tid, int32_t u, int32_t v, int32_t w, int32_t euv,
+                       int32_t euw, int32_t evw) {
+    topk_ctx* cx = (topk_ctx*)vctx;
+    const double* d = cx->g->d;
+    double s = orc_s(d[euv], d[euw], d[evw]);
+    if (orc_classify(s, 0.0) != cx->cls) return;
+    int32_t a = u, b = v, c = w, t;
+    if (b < a) { t = a; a = b; b = t; }
+    if (c < b) { t = b; b = c; c = t; }
+    if (b < a) { t = a; a = b; b = t; }
+    orc_stvec* x = &cx->v[tid];
+    if (x->len == x->cap) {
+        int64_t nc = x->cap ? 2 * x->cap : 1024;
+        orc_st* nb = (orc_st*)realloc(x->buf, sizeof(orc_st) * (size_t)nc);
+        if (!nb) { cx->fail[tid] = 1; return; }
+        x->buf = nb; x->cap = nc;
+    }
+    orc_st e = {s, a, b, c};
+    x->buf[x->len++] = e;
+}
+
+static int cmp_st_tri(const orc_st* x, const orc_st* y) {
+    if (x->a != y->a) return x->a < y->a ? -1 : 1;
+    if (x->b != y->b) return x->b < y->b ? -1 : 1;
+    if (x->c != y->c) return x->c < y->c ? -1 : 1;
+    return 0;
+}
+static int cmp_st_up(const void* p, const void* q) {
+    const orc_st *x = (const orc_st*)p, *y = (const orc_st*)q;
+    if (x->s != y->s) return x->s < y->s ? -1 : 1;
+    return cmp_st_tri(x, y);
+}
+static int cmp_st_down(const void* p, const void* q) {
+    const orc_st *x = (const orc_st*)p, *y = (const orc_st*)q;
+    if (x->s != y->s) return x->s > y->s ? -1 : 1;
+    return cmp_st_tri(x, y);
+}
+
+/* which = 1 (balanced) or 2 (unbalanced). tri [k][3], s [k]; *count = the number
+ * returned, min(k, #qualifying triangles). */
+int orc_topk(const orc_graph* g, int64_t k, int which, int32_t* tri, double* sv, int64_t* count) {
+    if (k < 0 || (which != 1 && which != 2)) return ORC_E_INVALID;
+    int th = orc_threads();
+    topk_ctx cx;
+    cx.g = g;
+    cx.cls = which;
+    cx.v = (orc_stvec*)calloc((size_t)th, sizeof(orc_stvec));
+    cx.fail = (int*)calloc((size_t)th, sizeof(int));
+    if (!cx.v || !cx.fail) { free(cx.v); free(cx.fail); return ORC_E_NOMEM; }
+    int rc = orc_node_iterate(g, topk_visit, &cx, th);
+    int64_t tot = 0;
+    for (int q = 0; q < th; q++) {
+        if (cx.fail[q]) rc = ORC_E_NOMEM;
+        tot += cx.v[q].len;
+    }
+    orc_st* all = NULL;
+    if (rc == ORC_OK && tot > 0) {
+        all = (orc_st*)malloc(sizeof(orc_st) * (size_t)tot);
+        if (!all) rc = ORC_E_NOMEM;
+    }
+    if (rc == ORC_OK) {
+        int64_t o = 0;
+        for (int q = 0; q < th; q++) {
+            if (cx.v[q].len) memcpy(all + o, cx.v[q].buf, sizeof(orc_st) * (size_t)cx.v[q].len);
+            o += cx.v[q].len;
+        }
+        if (tot > 0) qsort(all, (size_t)tot, sizeof(orc_st), which == 1 ? cmp_st_up : cmp_st_down);
+        int64_t r = tot < k ? tot : k;
+        for (int64_t i = 0; i < r; i++) {
+            tri[3 * i] = all[i].a; tri[3 * i + 1] = all[i].b; tri[3 * i + 2] = all[i].c;
+            sv[i] = all[i].s;
+        }
+        *count = r;
+    }
+    free(all);
+    for (int q = 0; q < th; q++) free(cx.v[q].buf);
+    free(cx.v); free(cx.fail);
+    return rc;
 }

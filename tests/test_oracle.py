@@ -365,6 +365,33 @@ def test_sample_edge_is_uniform():
     assert chi2 < 200  # 96 degrees of freedom; p ~ 1e-8 beyond this
 
 
+# ---------------------------------------------------------------- top-k
+
+@pytest.mark.parametrize("dist", ["dyadic16", "uniform", "tri"])
+def test_topk_matches_bruteforce(dist):
+    """Top-k search (Section 5): the k triangles with the highest P_bal among those with
+    P_bal >= 1/2 (the highest P_unbal among P_unbal > 1/2), ties by the sorted triple,
+    from the exact rational four-term P_bal over every vertex triple."""
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()):
+        p = inputs.draw_p(lo.shape[0], dist, 70 + gi)
+        g = load(n, lo, hi, p)
+        E = bf.edge_map(lo, hi, p)
+        tris = [(bf.p_bal(E[(i, j)], E[(i, k)], E[(j, k)]), (i, j, k)) for i, j, k in bf.triangles(n, E)]
+        bal = sorted([x for x in tris if x[0] >= F(1, 2)], key=lambda x: (-x[0], x[1]))
+        unb = sorted([x for x in tris if 1 - x[0] > F(1, 2)], key=lambda x: (x[0], x[1]))
+        for k in (0, 1, 3, len(tris) + 2):
+            for which, want in ((1, bal), (2, unb)):
+                tri, sv = g.topk(k, which)
+                assert [tuple(map(int, r)) for r in tri] == [w[1] for w in want[:k]], (dist, gi, k, which)
+                # s = 1 - 2 P_bal; exact for dyadic inputs, within a few ulps otherwise
+                for x, w in zip(sv, want[:k]):
+                    ref = 1 - 2 * w[0]
+                    if dist != "uniform":
+                        assert F(float(x)) == ref
+                    else:
+                        assert abs(F(float(x)) - ref) <= F(1, 2 ** 50)
+
+
 # ---------------------------------------------------------------- vertex sampling
 
 @pytest.mark.parametrize("gi", range(6))
