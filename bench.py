@@ -148,7 +148,17 @@ def main():
     log(f"count {counts} step {step_s * 1e3:.2f} ms, walk kernel {walk_ms:.2f} ms, "
         f"TEPS {teps:.3e}, B_alg {b_alg / 1e9:.1f} GB -> {achieved:.0f} GB/s")
 
+    # top-k search (Section 5) on the same graph: the 1,000 most balanced / unbalanced
+    tk = {}
+    for name, which in (("balanced", utri.UTRI_BAL), ("unbalanced", utri.UTRI_UNBAL)):
+        g.topk(1000, which)
+        ms, (tri, sv) = timed(lambda: g.topk(1000, which), 3, torch)
+        tk[name] = {"k": 1000, "ms": round(ms * 1e3, 2), "s_first": float(sv[0]),
+                    "s_last": float(sv[-1])}
+    log(f"top-1000 balanced {tk['balanced']['ms']} ms, unbalanced {tk['unbalanced']['ms']} ms")
+
     secondary = {
+        "topk": tk,
         "ingest_ms": round(load_ms, 2),
         "counts": {"balanced": counts[0], "unbalanced": counts[1]},
         "walk_kernel_ms": round(walk_ms, 3),
@@ -277,6 +287,20 @@ def run_secondary(args, torch, inputs, utri, dev):
     }
     log(f"batch {bt * 1e3:.1f} ms ({worlds / bt:.0f} worlds/s), 64 sequential counts "
         f"{seq_counts * 1e3:.1f} ms")
+    # vertex sampling (Section 6.1): 1,024 worlds x 1,000 vertices at the same thresholds
+    kv = 1000
+    g.sample(ts, kv, worlds, seed, utri.UTRI_SAMPLE_VERTEX)
+    vt, ves = timed(lambda: g.sample(ts, kv, worlds, seed, utri.UTRI_SAMPLE_VERTEX), 2, torch)
+    ves = ves.cpu().numpy()
+    vmape = np.where(exact > 0, np.abs(ves - exact[None]) / np.maximum(exact[None], 1), np.nan)
+    vmape = np.nanmean(vmape, axis=0)
+    out["vertex_sample_rmat_s20"] = {
+        "worlds": worlds, "vertices_per_world": kv, "taus": 64, "ms": vt * 1e3,
+        "worlds_per_s": worlds / vt, "vertex_samples_per_s": worlds * kv / vt,
+        "mape_bal_by_tau": [float(x) for x in vmape[:, 0]],
+        "mape_unbal_by_tau": [float(x) for x in vmape[:, 1]],
+    }
+    log(f"vertex sampling {vt * 1e3:.1f} ms ({worlds * kv / vt:.3e} vertex samples/s)")
     del g
     torch.cuda.empty_cache()
     # differentiation: expected count forward + edge-centric backward on R-MAT s22

@@ -165,6 +165,23 @@ int utri_vertex_local(utri_graph* g, const double* t, int nt, const int64_t* vid
                       int64_t* out, void* hip_stream);
 
 /*
+ * Top-k search (Section 5, "Adaption to Top-k Search"): which = UTRI_BAL gives the k
+ * triangles with the highest P_bal among those with P_bal >= 1/2 (the smallest
+ * s = d1 d2 d3), UTRI_UNBAL the k with the highest P_unbal among those with P_unbal > 1/2
+ * (the largest s); ties in s are broken by the sorted id triple, lexicographically.
+ * tri: device int32 [k][3] original ids sorted within each triple, in rank order;
+ * s: device FP64 [k], the canonical s of each (P_bal = (1 - s)/2); *count (host) = the
+ * number written, min(k, #qualifying triangles). The threshold is tightened as the
+ * paper describes, on the GPU by counting at 64 thresholds per walk (from t = 1
+ * downwards, so every walk prunes with Lemma 2) until the class count at the largest
+ * threshold still holding k triangles is small, then those candidates are enumerated,
+ * valued and sorted. Errors: UTRI_E_INVALID for k < 0, another `which`, or missing
+ * outputs. Waits for the stream.
+ */
+int utri_topk(utri_graph* g, int64_t k, int which, int32_t* tri, double* s, int64_t* count,
+              void* hip_stream);
+
+/*
  * Sampling estimators, `worlds` independent replicates of k uniform draws (with
  * replacement) each. Draw i of replicate w is Philox4x32-10 (Salmon et al., SC'11) with
  * key (seed_lo ^ w, seed_hi) and counter (i_lo, i_hi, 0, 0), mapped to the high 64 bits

@@ -516,6 +516,84 @@ int utri_vertex_local(utri_graph* g, const double* t, int nt, const int64_t* vid
     return UTRI_OK;
 }
 
+// Thresholds t_j = lo + (hi - lo) * j / 63, j = 0..63 (both ends included), and the class
+// counts at each.
+static int count_ladder(utri_graph* g, double lo, double hi, int cls, std::vector<double>& ts,
+                        std::vector<int64_t>& cnt, void* hip_stream) {
+    ts.resize(64);
+    for (int j = 0; j < 64; j++) ts[j] = std::min(1.0, std::max(0.5, lo + (hi - lo) * (j / 63.0)));
+    ts[63] = hi;
+    std::vector<int64_t> out(128);
+    UTRI_TRY(utri_count_batch(g, ts.data(), 64, UTRI_PRUNED, out.data(), hip_stream));
+    cnt.resize(64);
+    for (int j = 0; j < 64; j++) cnt[j] = out[2 * j + cls];
+    return UTRI_OK;
+}
+
+int utri_topk(utri_graph* g, int64_t k, int which, int32_t* tri, double* sv, int64_t* count,
+              void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (k < 0 || !count || (which != UTRI_BAL && which != UTRI_UNBAL) || (k > 0 && (!tri || !sv)))
+        return UTRI_E_INVALID;
+    *count = 0;
+    if (k == 0 || g->m == 0) return UTRI_OK;
+    hipStream_t s = as_stream(hip_stream);
+    const int cls = which == UTRI_BAL ? 0 : 1;
+    // 1. the largest threshold on a ladder whose class count is still >= k: the candidate
+    // set {s <= -c} (balanced) or {s > c} (unbalanced) there holds the top k; bands are
+    // tried from t = 1 down, so the walks prune as much as the answer allows (Lemma 2)
+    std::vector<double> ts;
+    std::vector<int64_t> cnt;
+    const double starts[3] = {0.95, 0.8, 0.5};
+    double lo = 0.5, hi = 1.0;
+    bool found = false;
+    for (int b = 0; b < 3 && !found; b++) {
+        lo = starts[b];
+        hi = b == 0 ? 1.0 : starts[b - 1];
+        UTRI_TRY(count_ladder(g, lo, hi, cls, ts, cnt, hip_stream));
+        found = cnt[0] >= k;
+    }
+    double tstar = 0.5;
+    int64_t nstar = cnt[0];  // fewer than k qualifying triangles: take them all
+    if (found) {
+        for (int round = 0; round < 8; round++) {
+            int j = 0;
+            while (j + 1 < 64 && cnt[j + 1] >= k) j++;
+            tstar = ts[j];
+            nstar = cnt[j];
+            const double nhi = j + 1 < 64 ? ts[j + 1] : hi;
+            if (nstar <= 2 * k + 4096 || !(nhi - tstar > 64 * 4e-16 * tstar)) break;
+            lo = tstar;
+            hi = nhi;
+            UTRI_TRY(count_ladder(g, lo, hi, cls, ts, cnt, hip_stream));
+        }
+    }
+    if (nstar == 0) return UTRI_OK;
+    // 2. enumerate the candidates at t*, lexicographically sorted
+    void *pt, *ps, *pk, *pi;
+    UTRI_TRY(utri_scratch(g, SCR_TOPK_TRI, sizeof(int32_t) * 3 * (size_t)nstar, &pt));
+    UTRI_TRY(utri_scratch(g, SCR_TOPK_S, sizeof(double) * (size_t)nstar, &ps));
+    UTRI_TRY(utri_scratch(g, SCR_TOPK_KEY, sizeof(uint64_t) * 2 * (size_t)nstar, &pk));
+    UTRI_TRY(utri_scratch(g, SCR_TOPK_IDX, sizeof(uint32_t) * 2 * (size_t)nstar, &pi));
+    int64_t ec[2] = {0, 0};
+    int32_t* list = (int32_t*)pt;
+    UTRI_TRY(utri_enumerate(g, tstar, UTRI_PRUNED, which, cls == 0 ? list : nullptr,
+                            cls == 0 ? nstar : 0, cls == 1 ? list : nullptr, cls == 1 ? nstar : 0,
+                            ec, 1, hip_stream));
+    const int64_t N = ec[cls];
+    if (N != nstar) return UTRI_E_HIP;  // the count and the list disagree: internal error
+    // 3. s and keys, a stable sort by key (ties keep the lexicographic order), first k
+    uint64_t* key = (uint64_t*)pk;
+    uint32_t* idx = (uint32_t*)pi;
+    UTRI_TRY(utri_topk_keys_launch(g, list, N, cls, (double*)ps, key, idx, s));
+    UTRI_TRY(radix_pairs(g, key, key + N, idx, idx + N, N, 64, s));
+    const int64_t r = std::min<int64_t>(k, N);
+    UTRI_TRY(utri_topk_gather_launch(list, (const double*)ps, idx + N, r, tri, sv, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    *count = r;
+    return UTRI_OK;
+}
+
 int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
                 int scheme, double* est, void* hip_stream) {
     UTRI_TRY(check_graph(g));

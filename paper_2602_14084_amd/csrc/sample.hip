@@ -65,25 +65,46 @@ __device__ __forceinline__ bool pass_draw(const SampleParams& sp, const SampleGr
     return lx > 0;
 }
 
+// When every active lane of the wave has the same group (the records of one sampled hub
+// vertex), one atomic serves them all; otherwise each lane does its own. Returns the
+// lane's slot offset from the value the atomic returned (for counting, unused).
+__device__ __forceinline__ int group_slot(int32_t* cnt, int32_t y, bool act, bool consume) {
+    const uint64_t am = __ballot(act);
+    if (am == 0) return 0;
+    const int lead = __ffsll((long long)am) - 1;
+    const int32_t y0 = __shfl(y, lead);
+    const uint64_t same = __ballot(act && y == y0);
+    if (same == am) {
+        const int nact = __popcll(am);
+        const int rank = __popcll(am & ((1ull << utri_lane()) - 1ull));
+        int base = 0;
+        if (utri_lane() == lead) base = consume ? atomicSub(&cnt[y0], nact) : atomicAdd(&cnt[y0], nact);
+        base = __shfl(base, lead);
+        return base - 1 - rank;  // consume: slots base-1, base-2, ... in lane order
+    }
+    if (!act) return 0;
+    return consume ? atomicSub(&cnt[y], 1) - 1 : atomicAdd(&cnt[y], 1);
+}
+
+// Lanes past the pass end take part in the wave-wide steps as inactive lanes.
 __global__ void k_s_count(SampleParams sp, SampleGraph G, const int32_t* __restrict__ slen,
                           int32_t* __restrict__ cnt) {
     const int64_t t = sp.t0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= sp.t1) return;
-    int64_t e;
-    int32_t world, y;
-    if (pass_draw(sp, G, slen, t, e, world, y)) atomicAdd(&cnt[y], 1);
+    int64_t e = 0;
+    int32_t world = 0, y = 0;
+    const bool act = t < sp.t1 && pass_draw(sp, G, slen, t, e, world, y);
+    (void)group_slot(cnt, y, act, false);
 }
 
 // Each draw takes a distinct slot of its group (the count is consumed downwards).
 __global__ void k_s_scatter(SampleParams sp, SampleGraph G, const int32_t* __restrict__ slen,
                             int32_t* __restrict__ cnt, int64_t* __restrict__ rec) {
     const int64_t t = sp.t0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= sp.t1) return;
-    int64_t e;
-    int32_t world, y;
-    if (!pass_draw(sp, G, slen, t, e, world, y)) return;
-    const int slot = atomicSub(&cnt[y], 1) - 1;
-    rec[sp.goff[y] + slot] = e | ((int64_t)world << 32);
+    int64_t e = 0;
+    int32_t world = 0, y = 0;
+    const bool act = t < sp.t1 && pass_draw(sp, G, slen, t, e, world, y);
+    const int slot = group_slot(cnt, y, act, true);
+    if (act) rec[sp.goff[y] + slot] = e | ((int64_t)world << 32);
 }
 
 // Items per group: ceil(draws / chunk), as work-group items when the probed prefix fits a
@@ -246,6 +267,40 @@ __global__ void __launch_bounds__(TPB) k_vertex_local(SampleGraph G, const int32
         }
         utri_wave_sync();
     }
+}
+
+// s of each listed triangle (original ids) from the per-row tables, and a key whose
+// ascending order is ascending s (descending s when desc); -0 and +0 get one key so they
+// tie, as their values do.
+__global__ void k_topk_keys(SampleGraph G, const int32_t* __restrict__ tri, int64_t N, int desc,
+                            double* __restrict__ sv, uint64_t* __restrict__ key,
+                            uint32_t* __restrict__ idx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t a = G.inv[tri[3 * i]], b = G.inv[tri[3 * i + 1]], c = G.inv[tri[3 * i + 2]];
+    const int64_t ab = sym_lookup(G.h_key, G.h_off[a], hbuckets_lg(G, a), b);
+    const int64_t ac = sym_lookup(G.h_key, G.h_off[a], hbuckets_lg(G, a), c);
+    const int64_t bc = sym_lookup(G.h_key, G.h_off[b], hbuckets_lg(G, b), c);
+    // the listed triples are triangles, so every lookup hits
+    const double s = utri_tri_s(ab >= 0 ? G.h_d[ab] : 0.0, ac >= 0 ? G.h_d[ac] : 0.0,
+                                bc >= 0 ? G.h_d[bc] : 0.0);
+    sv[i] = s;
+    uint64_t u = (uint64_t)__double_as_longlong(s == 0.0 ? 0.0 : s);
+    u = (u >> 63) ? ~u : (u | (1ull << 63));
+    key[i] = desc ? ~u : u;
+    idx[i] = (uint32_t)i;
+}
+
+__global__ void k_topk_gather(const int32_t* __restrict__ tri, const double* __restrict__ sv,
+                              const uint32_t* __restrict__ idx, int64_t r,
+                              int32_t* __restrict__ out_tri, double* __restrict__ out_s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r) return;
+    const int64_t j = idx[i];
+    out_tri[3 * i] = tri[3 * j];
+    out_tri[3 * i + 1] = tri[3 * j + 1];
+    out_tri[3 * i + 2] = tri[3 * j + 2];
+    out_s[i] = sv[j];
 }
 
 // hist [rows][2][nt+1] -> counts [rows][nt][2] (threshold order given by `order`) and
@@ -419,6 +474,24 @@ int utri_vertex_local_launch(utri_graph* g, const double* cvals, const int32_t* 
     const int blocks = (int)std::min<int64_t>((int64_t)g->num_cu * 8, (k + WPB - 1) / WPB);
     hipLaunchKernelGGL(k_vertex_local, dim3(blocks), dim3(TPB), 0, s, sample_graph(g),
                        (const int32_t*)slen, cvals, order, nt, vids, k, out);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+int utri_topk_keys_launch(utri_graph* g, const int32_t* tri, int64_t N, int desc, double* sv,
+                          uint64_t* key, uint32_t* idx, hipStream_t s) {
+    if (N <= 0) return UTRI_OK;
+    hipLaunchKernelGGL(k_topk_keys, dim3(blocks_for(N)), dim3(TPB), 0, s, sample_graph(g), tri, N,
+                       desc, sv, key, idx);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+int utri_topk_gather_launch(const int32_t* tri, const double* sv, const uint32_t* idx, int64_t r,
+                            int32_t* out_tri, double* out_s, hipStream_t s) {
+    if (r <= 0) return UTRI_OK;
+    hipLaunchKernelGGL(k_topk_gather, dim3(blocks_for(r)), dim3(TPB), 0, s, tri, sv, idx, r,
+                       out_tri, out_s);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

@@ -97,6 +97,10 @@ enum UtriScratch {
     SCR_VLEN,         // int32 [worlds * k] their Lemma-2 prefix lengths
     SCR_VOFF,         // int64 [worlds * k + 1] offsets of their edge records
     SCR_VREC,         // int64 edge records of the sampled vertices: edge | world << 32
+    SCR_TOPK_TRI,     // int32 [N][3] top-k candidates (enumerated at the found threshold)
+    SCR_TOPK_S,       // f64 [N] their s values
+    SCR_TOPK_KEY,     // u64 [2N] sort keys
+    SCR_TOPK_IDX,     // u32 [2N] sort values
     SCR_COUNT
 };
 
@@ -415,6 +419,12 @@ int utri_vertex_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, hi
                         int64_t* n_records);
 int utri_vertex_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
                              const int64_t* vids, int64_t k, int64_t* out, hipStream_t s);
+// Top-k: s of each listed triangle with its sort key (ascending s, or descending when
+// desc), then the first r entries of the sorted order.
+int utri_topk_keys_launch(utri_graph* g, const int32_t* tri, int64_t N, int desc, double* sv,
+                          uint64_t* key, uint32_t* idx, hipStream_t s);
+int utri_topk_gather_launch(const int32_t* tri, const double* sv, const uint32_t* idx, int64_t r,
+                            int32_t* out_tri, double* out_s, hipStream_t s);
 int utri_batch_launch(utri_graph* g, const WalkParams& wp, const int64_t* items,
                       const int64_t* n_items_dev, const int32_t* len, int64_t n_items_bound,
                       const SampleParams& sp, const int32_t* slen, hipStream_t s);

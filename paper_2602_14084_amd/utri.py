@@ -34,7 +34,7 @@ UTRI_SAMPLE_EDGE, UTRI_SAMPLE_VERTEX = 0, 1
 ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
-    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_sample", "utri_batch", "utri_autotune",
+    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sample", "utri_batch", "utri_autotune",
     "utri_walk_stats", "utri_timing", "utri_strerror",
 ]
 
@@ -70,6 +70,7 @@ def lib():
     L.utri_expected_grad.argtypes = [vp, vp, vp]
     L.utri_edge_local.argtypes = [vp, P(f64), C.c_int, vp, i64, vp, vp]
     L.utri_vertex_local.argtypes = [vp, P(f64), C.c_int, vp, i64, vp, vp]
+    L.utri_topk.argtypes = [vp, i64, C.c_int, vp, vp, P(i64), vp]
     L.utri_sample.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, C.c_int, vp, vp]
     L.utri_batch.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, vp, vp, C.c_int, vp]
     L.utri_autotune.argtypes = [vp, f64, C.c_char_p, vp]
@@ -237,6 +238,19 @@ def utri_vertex_local(h, ts, vids, stream=None):
     return out
 
 
+def utri_topk(h, k, which, stream=None):
+    """(triples [r,3] int32, s [r] f64) CUDA tensors of the top-k search, r <= k."""
+    torch = _torch()
+    tri = torch.empty((max(int(k), 1), 3), dtype=torch.int32, device="cuda")
+    sv = torch.empty(max(int(k), 1), dtype=torch.float64, device="cuda")
+    cnt = C.c_int64(0)
+    rc = lib().utri_topk(h, int(k), int(which), C.c_void_p(tri.data_ptr()),
+                         C.c_void_p(sv.data_ptr()), C.byref(cnt), _stream(stream))
+    _check(rc, "utri_topk")
+    r = int(cnt.value)
+    return tri[:r], sv[:r]
+
+
 def utri_sample(h, ts, k, worlds, seed, scheme=UTRI_SAMPLE_EDGE, stream=None):
     torch = _torch()
     a, pa = _f64_array(ts)
@@ -341,6 +355,9 @@ class Graph:
 
     def edge_local(self, ts, eids):
         return utri_edge_local(self._h, ts, eids)
+
+    def topk(self, k, which):
+        return utri_topk(self._h, k, which)
 
     def vertex_local(self, ts, vids):
         return utri_vertex_local(self._h, ts, vids)

@@ -9,6 +9,9 @@ properties that hold at any size; the scale-20 counts are compared whole.
 * R-MAT s23, bimodal P+: the pruned count at t = 0.8 equals a third of the sum of the
   per-edge local counts over all edges (each triangle has three edges); 2,000 sampled
   edges' local counts equal the oracle's.
+* R-MAT s20, P+ ~ Beta(2,2), vertex sampling at the benchmark's thresholds: the local
+  counts of all vertices sum to three times the exact counts; 8 worlds x 1,000 vertices
+  replay the oracle's estimates exactly.
 * R-MAT s22, P+ ~ U(0.05, 0.95): the gradient of 1,000 sampled edges (seed 3) equals the
   oracle's bit for bit and matches central finite differences at h = 1e-6 within 1e-6
   relative (local differences of the exact expected count: E is affine in each P+).
@@ -46,6 +49,28 @@ def test_rmat_s20_counts_match_oracle():
         for method in (utri.UTRI_PLAIN, utri.UTRI_PRUNED, utri.UTRI_PRUNED_L3):
             assert g.count(t, method) == tuple(want[j]), (t, method)
     assert np.array_equal(g.count_batch(ts), want)
+
+
+def test_rmat_s20_vertex_sampling():
+    n, lo, hi = inputs.rmat_graph(20, seed=1)
+    p = inputs.draw_p(lo.shape[0], "beta22", 2)
+    say("rmat20 vertex sampling m_in", lo.shape[0])
+    g = device_graph(n, lo, hi, p)
+    ts = [0.5 + 0.0075 * j for j in range(0, 64, 9)]
+    tot = np.zeros((len(ts), 2), np.int64)
+    step = 1 << 18
+    for v0 in range(0, n, step):
+        vids = torch.arange(v0, min(n, v0 + step), dtype=torch.int64, device="cuda")
+        tot += g.vertex_local(ts, vids).sum(dim=0).cpu().numpy()
+    want = g.count_batch(ts)
+    assert np.array_equal(tot, 3 * want), (tot, want)
+    est = g.sample(ts, 1000, 8, 2026, utri.UTRI_SAMPLE_VERTEX).cpu().numpy()
+    del g
+    torch.cuda.empty_cache()
+    say("oracle load")
+    og = oracle.load(n, lo, hi, p)
+    oest, _ = og.sample_vertices(ts, 1000, 8, 2026)
+    assert np.array_equal(est, oest)
 
 
 def test_rmat_s23_count_and_sampled_edge_locals():

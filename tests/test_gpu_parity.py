@@ -326,6 +326,52 @@ def test_vertex_sampler_edge_cases():
     assert g.vertex_local([0.6], np.zeros(0, np.int64)).shape == (0, 1, 2)
 
 
+@pytest.mark.parametrize("ci", [0, 2, 3, 4, 5, 6])
+def test_topk_matches_oracle(ci):
+    name, n, lo, hi = CASES[ci]
+    for dist in ("uniform", "bimodal", "certain", "dyadic16"):
+        p = inputs.draw_p(lo.shape[0], dist, 61 + ci)
+        og = oracle.load(n, lo, hi, p)
+        g = gpu_graph(n, lo, hi, p)
+        for k in (1, 7, 100, 5000):
+            for which in (utri.UTRI_BAL, utri.UTRI_UNBAL):
+                say("topk", name, dist, k, which)
+                tri, sv = g.topk(k, which)
+                wt, ws = og.topk(k, which)
+                assert np.array_equal(tri.cpu().numpy(), wt), (name, dist, k, which)
+                assert np.array_equal(sv.cpu().numpy(), ws), (name, dist, k, which)
+
+
+def test_topk_rmat16():
+    # many work items, a multi-round threshold search, k beyond the first band
+    n, lo, hi = inputs.rmat_graph(16, seed=5)
+    p = inputs.draw_p(lo.shape[0], "beta22", 8)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    for k, which in [(1000, utri.UTRI_BAL), (20000, utri.UTRI_UNBAL), (3, utri.UTRI_BAL)]:
+        say("topk rmat16", k, which)
+        tri, sv = g.topk(k, which)
+        wt, ws = og.topk(k, which)
+        assert np.array_equal(tri.cpu().numpy(), wt) and np.array_equal(sv.cpu().numpy(), ws)
+
+
+def test_topk_edge_cases():
+    e = gpu_graph(5, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0))
+    tri, sv = e.topk(10, utri.UTRI_BAL)
+    assert tri.shape[0] == 0 and sv.shape[0] == 0
+    # three likely-positive edges: d = 1 - 2(0.9) < 0 each, s < 0, balanced only
+    g = gpu_graph(3, np.array([0, 0, 1]), np.array([1, 2, 2]), np.array([0.9, 0.9, 0.9]))
+    assert g.topk(0, utri.UTRI_BAL)[0].shape[0] == 0
+    tri, sv = g.topk(3, utri.UTRI_BAL)
+    d = 1.0 - 2.0 * 0.9
+    assert tri.cpu().tolist() == [[0, 1, 2]] and float(sv[0]) == (d * d) * d
+    assert g.topk(3, utri.UTRI_UNBAL)[0].shape[0] == 0
+    for bad in [(-1, utri.UTRI_BAL), (3, utri.UTRI_BOTH), (3, 0)]:
+        with pytest.raises(utri.UtriError) as ei:
+            g.topk(*bad)
+        assert ei.value.code == utri.UTRI_E_INVALID
+
+
 def test_batch_eager_and_graph_replays():
     n, lo, hi = inputs.rmat_graph(13, seed=9)
     p = inputs.draw_p(lo.shape[0], "beta22", 2)
