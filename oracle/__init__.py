@@ -56,6 +56,9 @@ def _load():
     lib.orc_sample_vertices.argtypes = [vp, _f64p, C.c_int, C.c_int64, C.c_int32, C.c_uint64,
                                         _f64p, _i64p]
     lib.orc_topk.argtypes = [vp, C.c_int64, C.c_int, _i32p, _f64p, _i64p]
+    lib.orc_sign_negative.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_double]
+    lib.orc_sign_negative.restype = C.c_int
+    lib.orc_sign_worlds.argtypes = [vp, C.c_int32, C.c_uint64, _i64p]
     lib.orc_num_threads.restype = C.c_int
     _lib = lib
     return lib
@@ -250,6 +253,15 @@ class OracleGraph:
         return tri[:r].copy(), sv[:r].copy()
 
 
+    def sign_worlds(self, worlds, seed):
+        """Balanced triangles in each of `worlds` sampled sign worlds: int64 [worlds]."""
+        out = np.zeros(worlds, np.int64)
+        rc = self._lib.orc_sign_worlds(self._h, int(worlds), C.c_uint64(seed), _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "sign_worlds")
+        return out
+
+
 def load(n, src, dst, p) -> OracleGraph:
     return OracleGraph(n, src, dst, p)
 
@@ -269,3 +281,7 @@ def sample_edge(seed, world, i, m) -> int:
 
 def sample_vertex(seed, world, i, n) -> int:
     return int(_load().orc_sample_vertex(C.c_uint64(seed), C.c_uint32(world), C.c_uint64(i), int(n)))
+
+
+def sign_negative(seed, e, w, p) -> int:
+    return int(_load().orc_sign_negative(C.c_uint64(seed), int(e), int(w), float(p)))

@@ -51,6 +51,13 @@
  *    s <= 0) the k with the highest P_bal, i.e. the smallest s; among the unbalanced ones
  *    (P_unbal > 1/2, s > 0) the k with the largest s. Ties in s are broken by the sorted
  *    id triple, lexicographically; fewer than k qualifying triangles give all of them.
+ *  - orc_sign_worlds: possible-world Monte-Carlo of the expected balanced count. The
+ *    model of Section 3 makes every edge independently positive with probability
+ *    P+(e); world w draws each edge's sign from Philox4x32-10 with key (seed_lo,
+ *    seed_hi) and counter (e, w / 4, 1, 0), word w % 4 = u, positive iff
+ *    u < P+(e) * 2^32. A triangle is balanced in a world iff it has an even number of
+ *    negative edges; counts[w] is the number of balanced triangles of world w, whose
+ *    mean over worlds estimates E = sum of P_bal without bias.
  *  - orc_sample_vertices: Algorithm "Baseline Vertex Sampling" (Section 6.1) with
  *    exactly k uniform draws with replacement; the estimate is n * (sum of local
  *    counts) / (3k). Vertex draw i of world w is the Philox block of edge draw i of
@@ -919,5 +926,58 @@ int orc_topk(const orc_graph* g, int64_t k, int which, int32_t* tri, double* sv,
     free(all);
     for (int q = 0; q < th; q++) free(cx.v[q].buf);
     free(cx.v); free(cx.fail);
+    return rc;
+}
+
+/* ---------------------------------------------------------------- sign worlds */
+
+/* 1 if edge e (P+ = p) is negative in world w */
+int orc_sign_negative(uint64_t seed, int64_t e, int32_t w, double p) {
+    uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(w / 4), 1u, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    return (double)x[w % 4] < p * 4294967296.0 ? 0 : 1;
+}
+
+typedef struct {
+    const orc_graph* g;
+    const uint8_t* neg;   /* [m][worlds] */
+    int32_t worlds;
+    int64_t* cnt;         /* [threads][worlds] */
+} sign_ctx;
+
+static void sign_visit(void* vctx, int tid, int32_t u, int32_t v, int32_t w, int32_t euv,
+                       int32_t euw, int32_t evw) {
+    sign_ctx* cx = (sign_ctx*)vctx;
+    (void)u; (void)v; (void)w;
+    const int32_t W = cx->worlds;
+    const uint8_t* a = cx->neg + (size_t)euv * W;
+    const uint8_t* b = cx->neg + (size_t)euw * W;
+    const uint8_t* c = cx->neg + (size_t)evw * W;
+    int64_t* cnt = cx->cnt + (size_t)tid * W;
+    for (int32_t q = 0; q < W; q++)
+        if (((a[q] + b[q] + c[q]) & 1) == 0) cnt[q]++;
+}
+
+int orc_sign_worlds(const orc_graph* g, int32_t worlds, uint64_t seed, int64_t* counts) {
+    if (worlds <= 0) return ORC_E_INVALID;
+    uint8_t* neg = (uint8_t*)malloc((size_t)(g->m > 0 ? g->m : 1) * (size_t)worlds);
+    int th = orc_threads();
+    int64_t* cnt = (int64_t*)calloc((size_t)th * (size_t)worlds, sizeof(int64_t));
+    if (!neg || !cnt) { free(neg); free(cnt); return ORC_E_NOMEM; }
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < g->m; e++)
+        for (int32_t q = 0; q < worlds; q++)
+            neg[(size_t)e * worlds + q] = (uint8_t)orc_sign_negative(seed, e, q, g->p[e]);
+    sign_ctx cx = {g, neg, worlds, cnt};
+    int rc = orc_node_iterate(g, sign_visit, &cx, th);
+    for (int32_t q = 0; q < worlds; q++) {
+        int64_t t = 0;
+        for (int i = 0; i < th; i++) t += cnt[(size_t)i * worlds + q];
+        counts[q] = t;
+    }
+    free(neg);
+    free(cnt);
     return rc;
 }

@@ -365,6 +365,63 @@ def test_sample_edge_is_uniform():
     assert chi2 < 200  # 96 degrees of freedom; p ~ 1e-8 beyond this
 
 
+# ---------------------------------------------------------------- sign worlds
+
+def test_sign_convention():
+    """World w of edge e: Philox block with key (seed_lo, seed_hi), counter (e, w // 4, 1, 0);
+    word w % 4 = u; positive iff u < P+ * 2^32 (compared exactly)."""
+    for seed, e, w, p in [(0x0123456789ABCDEF, 0, 0, 0.3), (5, 12345, 1023, 0.999),
+                          (2 ** 64 - 1, 7, 6, 0.5), (9, 3, 2, 0.0), (9, 3, 2, 1.0)]:
+        x = oracle.philox4x32_10([e, w // 4, 1, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        pos = F(int(x[w % 4])) < F(p) * 2 ** 32
+        assert oracle.sign_negative(seed, e, w, p) == (0 if pos else 1)
+    # frequency of positive signs matches P+ (binomial, 4 sigma)
+    for p in (0.1, 0.5, 0.77):
+        k = sum(1 - oracle.sign_negative(3, e, q, p) for e in range(40) for q in range(100))
+        assert abs(k - 4000 * p) <= 4 * np.sqrt(4000 * p * (1 - p))
+
+
+def test_sign_worlds_bruteforce():
+    """Per-world balanced counts equal a brute force over all triples with the signs
+    recomputed from the Philox convention."""
+    for gi in (0, 2, 4):
+        n, lo, hi = tiny_graphs()[gi]
+        p = inputs.draw_p(lo.shape[0], "uniform", 90 + gi)
+        g = load(n, lo, hi, p)
+        W, seed = 64, 0xABCDEF0123 + gi
+        got = g.sign_worlds(W, seed)
+        clo, chi, cp = g.edges()
+        eid = {(int(a), int(b)): e for e, (a, b) in enumerate(zip(clo, chi))}
+        E = {k: None for k in eid}
+        want = np.zeros(W, np.int64)
+        for q in range(W):
+            neg = {k: oracle.sign_negative(seed, e, q, cp[e]) for k, e in eid.items()}
+            for i, j, k in bf.triangles(n, E):
+                if (neg[(i, j)] + neg[(i, k)] + neg[(j, k)]) % 2 == 0:
+                    want[q] += 1
+        assert np.array_equal(got, want), gi
+
+
+def test_sign_worlds_special_cases_and_unbiased():
+    n, lo, hi = inputs.chung_lu_graph()
+    # certain signs: every world is the deterministic signed graph
+    p = inputs.draw_p(lo.shape[0], "certain", 5)
+    g = load(n, lo, hi, p)
+    got = g.sign_worlds(64, 17)
+    assert np.all(got == g.count(1.0)[0])
+    # all P+ = 1/2: the mean is T/2
+    T = int(g.count(0.5)[0] + g.count(0.5)[1])
+    g = load(n, lo, hi, np.full(lo.shape[0], 0.5))
+    got = g.sign_worlds(1024, 18).astype(np.float64)
+    assert abs(got.mean() - T / 2) <= 4 * got.std(ddof=1) / np.sqrt(1024)
+    # uniform P+: the mean over worlds estimates E without bias
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    g = load(n, lo, hi, p)
+    got = g.sign_worlds(1024, 19).astype(np.float64)
+    E = g.expected()[0]
+    assert abs(got.mean() - E) <= 4 * got.std(ddof=1) / np.sqrt(1024), (got.mean(), E)
+
+
 # ---------------------------------------------------------------- top-k
 
 @pytest.mark.parametrize("dist", ["dyadic16", "uniform", "tri"])
