@@ -313,6 +313,15 @@ def run_secondary(args, torch, inputs, utri, dev):
     fwd, E = timed(lambda: g.expected(), max(2, args.steps), torch)
     bwd, _ = timed(lambda: g.expected_grad(grad), max(2, args.steps), torch)
     cnt, _ = timed(lambda: g.count(0.5, utri.UTRI_PLAIN), 2, torch)
+    # possible-world sign Monte-Carlo of E: 1,024 worlds
+    g.sign_worlds(1024, 7)
+    swt, sw = timed(lambda: g.sign_worlds(1024, 7), 2, torch)
+    sw = sw.cpu().numpy().astype(np.float64)
+    out["sign_worlds_rmat_s22"] = {"worlds": 1024, "ms": swt * 1e3, "worlds_per_s": 1024 / swt,
+                                   "mean": float(sw.mean()), "exact_expected": E,
+                                   "rel_error_of_mean": float(abs(sw.mean() - E) / E),
+                                   "rel_std_error": float(sw.std(ddof=1) / np.sqrt(1024) / E)}
+    log(f"s22 sign worlds {swt * 1e3:.1f} ms for 1024 worlds")
     out["diff_rmat_s22"] = {"expected": E, "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
                             "backward_over_forward": bwd / fwd,
                             "plain_count_ms": cnt * 1e3, "m": g.m}

@@ -165,6 +165,19 @@ int utri_vertex_local(utri_graph* g, const double* t, int nt, const int64_t* vid
                       int64_t* out, void* hip_stream);
 
 /*
+ * Possible-world Monte-Carlo of the expected balanced count (the possible-world model of
+ * Section 3: every edge independently positive with probability P+). Sign world w of
+ * edge e uses Philox4x32-10 with key (seed_lo, seed_hi) and counter (e, w / 4, 1, 0):
+ * word w % 4 = u, the edge is positive iff u < P+(e) * 2^32. A triangle is balanced in
+ * a world iff it has an even number of negative edges. counts: device int64 [worlds],
+ * the balanced triangles of each world (their mean estimates E without bias; the exact
+ * E is utri_expected). worlds: 32, 64, 128, 256, 512 or 1024 (UTRI_E_INVALID
+ * otherwise). Needs 4 * m * worlds / 32 bytes of device scratch. Waits for the stream.
+ */
+int utri_sign_worlds(utri_graph* g, int32_t worlds, uint64_t seed, int64_t* counts,
+                     void* hip_stream);
+
+/*
  * Top-k search (Section 5, "Adaption to Top-k Search"): which = UTRI_BAL gives the k
  * triangles with the highest P_bal among those with P_bal >= 1/2 (the smallest
  * s = d1 d2 d3), UTRI_UNBAL the k with the highest P_unbal among those with P_unbal > 1/2

@@ -289,6 +289,8 @@ int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int
     if (rc != UTRI_OK) return rc;
     apply_cache(g, getenv("UTRI_TUNE_CACHE"));
     if (const char* e = getenv("UTRI_WALK_BLOCKS_PER_CU")) g->walk_blocks_per_cu = std::max(0, atoi(e));
+    if (const char* e = getenv("UTRI_SIGN_FLUSH"))
+        g->sign_flush_at = (uint32_t)std::max<long long>(1, std::min<long long>(65535, atoll(e)));
     if (const char* e = getenv("UTRI_SAMPLE_PASS"))
         g->sample_pass = std::max<int64_t>(64, std::min<int64_t>(UTRI_SAMPLE_PASS, atoll(e)));
     *out = g;
@@ -456,6 +458,34 @@ int utri_expected(utri_graph* g, double* E, void* hip_stream) {
     const unsigned __int128 S = ((unsigned __int128)h[2] << 64) | (unsigned __int128)h[1];
     const unsigned __int128 N = (T << 62) - S;
     *E = utri_i128_to_double((int64_t)(uint64_t)(N >> 64), (uint64_t)N) * 0x1p-63;
+    return UTRI_OK;
+}
+
+int utri_sign_worlds(utri_graph* g, int32_t worlds, uint64_t seed, int64_t* counts,
+                     void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!counts || worlds < 32 || worlds > 1024 || (worlds & (worlds - 1)) != 0)
+        return UTRI_E_INVALID;
+    hipStream_t s = as_stream(hip_stream);
+    const int ww = worlds / 32;
+    void *pm, *pc;
+    UTRI_TRY(utri_scratch(g, SCR_SIGN_MASK, sizeof(uint32_t) * (size_t)std::max<int64_t>(1, g->m * ww), &pm));
+    UTRI_TRY(utri_scratch(g, SCR_SIGN_CNT, sizeof(uint64_t) * (size_t)worlds, &pc));
+    UTRI_TRY(utri_fill_u64(pc, 0, worlds, s));
+    UTRI_TRY(utri_sign_masks_launch(g, seed, ww, (uint32_t*)pm, s));
+    int64_t *items, *nitems;
+    int32_t* len;
+    UTRI_TRY(utri_walk_prepare(g, 0.0, 0, s, &items, &nitems, &len));
+    WalkParams wp;
+    wp.o_eid = g->o_eid;
+    wp.masks = (const uint32_t*)pm;
+    wp.ww = ww;
+    wp.wcount = (unsigned long long*)pc;
+    wp.sign_flush_at = g->sign_flush_at;
+    UTRI_TRY(utri_walk_launch(g, WALK_SIGN, wp, items, nitems, len, 0, s));
+    UTRI_HIP_TRY(hipMemcpyAsync(counts, pc, sizeof(int64_t) * (size_t)worlds,
+                                hipMemcpyDeviceToDevice, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
     return UTRI_OK;
 }
 

@@ -101,6 +101,8 @@ enum UtriScratch {
     SCR_TOPK_S,       // f64 [N] their s values
     SCR_TOPK_KEY,     // u64 [2N] sort keys
     SCR_TOPK_IDX,     // u32 [2N] sort values
+    SCR_SIGN_MASK,    // u32 [m][worlds / 32] negative-sign masks of the sign worlds
+    SCR_SIGN_CNT,     // u64 [worlds] balanced triangles per sign world
     SCR_COUNT
 };
 
@@ -161,6 +163,7 @@ struct utri_graph {
     int sample_blocks_per_cu = 8;
     int sample_chunk = 128;         // draws per sampler group item
     int64_t sample_pass = UTRI_SAMPLE_PASS;  // draws grouped per sampler pass
+    uint32_t sign_flush_at = 65535;          // sign-world counter additions between flushes
 
     // gradient: item counts of its four lists and partial-slice totals (they depend on the
     // degrees only), -1 = not read yet
@@ -354,6 +357,7 @@ enum WalkMode {
     WALK_ENUM_COUNT = 3,
     WALK_ENUM_FILL = 4,
     WALK_STATS = 5,  // acc[0] = hash hits, acc[1] = target elements (first chunk), acc[2] = all streamed
+    WALK_SIGN = 6,   // wcount[w] += balanced triangles of sign world w
 };
 
 struct WalkParams {
@@ -378,7 +382,17 @@ struct WalkParams {
     int idbits = 31;
     int mb = 0;
     float c_up = 0.f, c_dn = 0.f;
+    // SIGN: per-edge negative-sign masks [m][ww] (bit b of word j: world 32 j + b), the
+    // oriented rows' edge ids, and the per-world counters
+    const int32_t* o_eid = nullptr;
+    const uint32_t* masks = nullptr;
+    int ww = 0;
+    unsigned long long* wcount = nullptr;
+    uint32_t sign_flush_at = 65535;  // additions between counter flushes (<= 2^16 - 1)
 };
+
+// Negative-sign masks of `ww` words per edge (worlds 32 ww) for the sign-world walk.
+int utri_sign_masks_launch(utri_graph* g, uint64_t seed, int ww, uint32_t* masks, hipStream_t s);
 
 int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp, const int64_t* items,
                      const int64_t* n_items_dev, const int32_t* len, int64_t n_items_host_bound,

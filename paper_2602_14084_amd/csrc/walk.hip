@@ -18,8 +18,15 @@
 //   length broadcast in scalar registers; each lane loads up to four ids ahead (64
 //   apart) before probing them, so every wave keeps several loads in flight. Hits are
 //   classified from the d codes packed above the ids; only the few the codes leave
-//   undecided read d values. The classify, count, histogram, fixed-point, enumeration
-//   and statistics epilogues are selected at compile time.
+//   undecided read d values. The classify, count, histogram, fixed-point, enumeration,
+//   sign-world and statistics epilogues are selected at compile time.
+//
+// Sign worlds (possible-world Monte-Carlo of E): every triangle's three edge ids go to a
+// per-wave LDS queue; a full queue is drained with lanes over world words (world
+// 32 j + b is bit b of mask word j): the balanced worlds of a triangle are the zero bits
+// of the XOR of its three negative-sign masks, added into per-lane bit-sliced counters
+// (SIGN_K bit planes in registers) that are flushed to the per-world totals when they
+// could overflow and when the wave ends.
 #include <algorithm>
 
 #include "walk_common.h"
@@ -98,13 +105,71 @@ __global__ void k_items(const int32_t* __restrict__ lcnt, const int32_t* __restr
     for (int k = 0; k < c; k++) items[o + k] = ((int64_t)k << 32) | (int64_t)v;
 }
 
+constexpr int SIGN_K = 16;   // bit planes of the sign-world counters (flush before 2^16)
+constexpr int SIGN_Q = 128;  // triangles queued per wave
+
 struct WalkLaneState {
     uint64_t nb = 0, nu = 0;       // COUNT / ENUM_COUNT
     uint64_t tri = 0;              // EXPECTED / STATS
     uint64_t slo = 0;              // EXPECTED: sum of low 32 bits of each fixed-point term
     int64_t shi = 0;               // EXPECTED: sum of the terms shifted right by 32
     uint64_t wt = 0, wt_all = 0;   // STATS: streamed target elements (first chunk / all)
+    uint32_t bs[SIGN_K] = {};      // SIGN: bit planes of this lane's 32 world counters
+    uint32_t npass = 0;            // SIGN: additions since the last flush (wave-uniform)
+    int qn = 0;                    // SIGN: queued triangles (wave-uniform)
 };
+
+// SIGN: per-wave queue of triangles as their three edge ids
+struct SignQueue {
+    int32_t e[3][SIGN_Q];
+};
+__shared__ SignQueue sign_q[WPB];
+
+// Add this lane's 32 counters into the per-world totals and clear them.
+__device__ __forceinline__ void sign_flush(const WalkParams& wp, WalkLaneState& st) {
+    const int wd = utri_lane() % wp.ww;
+    for (int b = 0; b < 32; b++) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int i = 0; i < SIGN_K; i++) v |= ((st.bs[i] >> b) & 1u) << i;
+        if (v) atomicAdd(&wp.wcount[wd * 32 + b], (unsigned long long)v);
+    }
+#pragma unroll
+    for (int i = 0; i < SIGN_K; i++) st.bs[i] = 0;
+    st.npass = 0;
+}
+
+// Count the queued triangles into the lanes' counters and empty the queue. Lane l takes
+// word l % ww of triangle l / ww of each group of 64 / ww triangles.
+__device__ __forceinline__ void sign_drain(const WalkParams& wp, WalkLaneState& st) {
+    SignQueue& Q = sign_q[threadIdx.x / UTRI_WAVE];
+    const int lane = utri_lane();
+    const int ww = wp.ww;
+    const int tp = UTRI_WAVE / ww;
+    const int ti = lane / ww, wd = lane % ww;
+    utri_wave_sync();
+    for (int b0 = 0; b0 < st.qn; b0 += tp) {
+        const int t = b0 + ti;
+        uint32_t c = 0;
+        if (t < st.qn) {
+            const uint32_t x = wp.masks[(int64_t)Q.e[0][t] * ww + wd] ^
+                               wp.masks[(int64_t)Q.e[1][t] * ww + wd] ^
+                               wp.masks[(int64_t)Q.e[2][t] * ww + wd];
+            c = ~x;  // worlds with an even number of negative edges
+        }
+        // ripple-carry add of the 32 one-bit values into the bit planes
+#pragma unroll
+        for (int i = 0; i < SIGN_K; i++) {
+            if (__ballot(c != 0) == 0) break;
+            const uint32_t carry = st.bs[i] & c;
+            st.bs[i] ^= c;
+            c = carry;
+        }
+        if (++st.npass >= wp.sign_flush_at) sign_flush(wp, st);
+    }
+    st.qn = 0;
+    utri_wave_sync();
+}
 
 // The staged source chunk and the current pair (u, v).
 struct RowCtx {
@@ -197,6 +262,8 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             const int j = j0 + k * UTRI_WAVE + lane;
             const uint32_t w = pw[k] & wp.idmask;
             bool is_b = false, is_u = false;
+            bool sg = false;
+            int32_t euw = 0, evw = 0;
             // kk: the matching packed key, 0 if none; h: its slot
             int h;
             const int kk = bucket_find(R.key, R.lg, R.mask, w, wp.idmask, h);
@@ -204,6 +271,10 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                 const uint32_t hkey = (uint32_t)kk;
                 if (MODE == WALK_STATS) {
                     st.tri++;
+                } else if (MODE == WALK_SIGN) {
+                    sg = true;
+                    euw = wp.o_eid[R.src_base + R.pos[h]];
+                    evw = wp.o_eid[ovs + j];
                 } else {
                     int dec = -1;
                     if (kCoded && wp.mb > 0)
@@ -232,6 +303,21 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                         is_b = (dec == 1) && (wp.which & UTRI_BAL);
                         is_u = (dec == 2) && (wp.which & UTRI_UNBAL);
                     }
+                }
+            }
+            if (MODE == WALK_SIGN) {
+                // queue this sub-strip's triangles (pv carries the edge id of u -> v)
+                const uint64_t hm = __ballot(sg);
+                if (hm) {
+                    if (sg) {
+                        SignQueue& Q = sign_q[threadIdx.x / UTRI_WAVE];
+                        const int slot = st.qn + __popcll(hm & __lanemask_lt());
+                        Q.e[0][slot] = pv;
+                        Q.e[1][slot] = euw;
+                        Q.e[2][slot] = evw;
+                    }
+                    st.qn += __popcll(hm);
+                    if (st.qn >= SIGN_Q - UTRI_WAVE) sign_drain(wp, st);
                 }
             }
             if (MODE == WALK_ENUM_FILL) {
@@ -340,11 +426,13 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
         double duv;
         CodeRow cr;
         load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv, cr);
+        const int euv = (MODE == WALK_SIGN && i0 + lane < Lu) ? wp.o_eid[ou + i0 + lane] : 0;
         const int nv = min(UTRI_WAVE, Lu - i0);
         for (int si = 0; si < nv; si++) {
             const int lvs = bcast_i32(lv, si);
             if (lvs == 0) continue;
-            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)] : 0;
+            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
+                               : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
                               (uint32_t)bcast_i32((int)cr.klo, si),
                               bcast_i32(cr.neg_a ? 1 : 0, si) != 0};
@@ -395,11 +483,13 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
         double duv;
         CodeRow cr;
         load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv, cr);
+        const int euv = (MODE == WALK_SIGN && i0 + lane < Lu) ? wp.o_eid[ou + i0 + lane] : 0;
         const int nv = min(UTRI_WAVE, Lu - i0);
         for (int si = wib; si < nv; si += WPB) {
             const int lvs = bcast_i32(lv, si);
             if (lvs == 0) continue;
-            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)] : 0;
+            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
+                               : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
                               (uint32_t)bcast_i32((int)cr.klo, si),
                               bcast_i32(cr.neg_a ? 1 : 0, si) != 0};
@@ -445,6 +535,9 @@ __device__ void walk_flush(const WalkParams& wp, const double* __restrict__ o_d,
             atomicAdd(&wp.acc[1], (unsigned long long)b);
             atomicAdd(&wp.acc[2], (unsigned long long)c);
         }
+    } else if (MODE == WALK_SIGN) {
+        if (st.qn > 0) sign_drain(wp, st);
+        sign_flush(wp, st);
     } else if (MODE == WALK_HIST) {
         utri_wave_sync();
         for (int q = lane; q < 2 * NB; q += UTRI_WAVE) {
@@ -662,6 +755,7 @@ int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int
         case WALK_ENUM_COUNT: launch_walk<WALK_ENUM_COUNT>(g, wp, len, items, n_items_dev, s); break;
         case WALK_ENUM_FILL: launch_walk<WALK_ENUM_FILL>(g, wp, len, items, n_items_dev, s); break;
         case WALK_STATS: launch_walk<WALK_STATS>(g, wp, len, items, n_items_dev, s); break;
+        case WALK_SIGN: launch_walk<WALK_SIGN>(g, wp, len, items, n_items_dev, s); break;
         default: return UTRI_E_INVALID;
     }
     UTRI_HIP_TRY(hipGetLastError());
@@ -682,6 +776,39 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     const int blocks = g->num_cu * blocks_per_cu(g, k_batch);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj, g->o_d,
                        len, g->perm, items, n_items_dev, sp, G, slen);
+    UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+namespace {
+
+// Thread per (edge, mask word): 8 Philox blocks of 4 worlds each; bit 4 r + q of word j
+// is world 32 j + 4 r + q, set when the edge is negative there (u >= P+ * 2^32).
+__global__ void k_sign_masks(const double* __restrict__ e_p, int64_t m, uint64_t seed, int ww,
+                             uint32_t* __restrict__ masks) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * ww) return;
+    const int64_t e = t / ww;
+    const int j = (int)(t - e * ww);
+    const double th = e_p[e] * 4294967296.0;
+    uint32_t mk = 0;
+    for (int r = 0; r < 8; r++) {
+        uint32_t x[4];
+        utri_philox((uint32_t)e, (uint32_t)(8 * j + r), 1u, 0u, (uint32_t)seed,
+                    (uint32_t)(seed >> 32), x);
+#pragma unroll
+        for (int q = 0; q < 4; q++) mk |= ((double)x[q] < th ? 0u : 1u) << (4 * r + q);
+    }
+    masks[t] = mk;
+}
+
+}  // namespace
+
+int utri_sign_masks_launch(utri_graph* g, uint64_t seed, int ww, uint32_t* masks, hipStream_t s) {
+    const int64_t tot = g->m * ww;
+    if (tot == 0) return UTRI_OK;
+    hipLaunchKernelGGL(k_sign_masks, dim3(blocks_for(tot)), dim3(TPB), 0, s, (const double*)g->e_p,
+                       g->m, seed, ww, masks);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

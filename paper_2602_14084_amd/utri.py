@@ -34,7 +34,7 @@ UTRI_SAMPLE_EDGE, UTRI_SAMPLE_VERTEX = 0, 1
 ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
-    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sample", "utri_batch", "utri_autotune",
+    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sign_worlds", "utri_sample", "utri_batch", "utri_autotune",
     "utri_walk_stats", "utri_timing", "utri_strerror",
 ]
 
@@ -71,6 +71,7 @@ def lib():
     L.utri_edge_local.argtypes = [vp, P(f64), C.c_int, vp, i64, vp, vp]
     L.utri_vertex_local.argtypes = [vp, P(f64), C.c_int, vp, i64, vp, vp]
     L.utri_topk.argtypes = [vp, i64, C.c_int, vp, vp, P(i64), vp]
+    L.utri_sign_worlds.argtypes = [vp, i32, u64, vp, vp]
     L.utri_sample.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, C.c_int, vp, vp]
     L.utri_batch.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, vp, vp, C.c_int, vp]
     L.utri_autotune.argtypes = [vp, f64, C.c_char_p, vp]
@@ -238,6 +239,16 @@ def utri_vertex_local(h, ts, vids, stream=None):
     return out
 
 
+def utri_sign_worlds(h, worlds, seed, stream=None):
+    """Balanced triangles in each sampled sign world: int64 CUDA tensor [worlds]."""
+    torch = _torch()
+    out = torch.empty(int(worlds), dtype=torch.int64, device="cuda")
+    rc = lib().utri_sign_worlds(h, int(worlds), C.c_uint64(seed), C.c_void_p(out.data_ptr()),
+                                _stream(stream))
+    _check(rc, "utri_sign_worlds")
+    return out
+
+
 def utri_topk(h, k, which, stream=None):
     """(triples [r,3] int32, s [r] f64) CUDA tensors of the top-k search, r <= k."""
     torch = _torch()
@@ -355,6 +366,9 @@ class Graph:
 
     def edge_local(self, ts, eids):
         return utri_edge_local(self._h, ts, eids)
+
+    def sign_worlds(self, worlds, seed):
+        return utri_sign_worlds(self._h, worlds, seed)
 
     def topk(self, k, which):
         return utri_topk(self._h, k, which)

@@ -12,6 +12,8 @@ properties that hold at any size; the scale-20 counts are compared whole.
 * R-MAT s20, P+ ~ Beta(2,2), vertex sampling at the benchmark's thresholds: the local
   counts of all vertices sum to three times the exact counts; 8 worlds x 1,000 vertices
   replay the oracle's estimates exactly.
+* R-MAT s20, P+ ~ Beta(2,2), sign worlds: 32 worlds equal the oracle's counts exactly;
+  the mean of 1,024 worlds is within 4 standard errors of the exact expected count.
 * R-MAT s22, P+ ~ U(0.05, 0.95): the gradient of 1,000 sampled edges (seed 3) equals the
   oracle's bit for bit and matches central finite differences at h = 1e-6 within 1e-6
   relative (local differences of the exact expected count: E is affine in each P+).
@@ -71,6 +73,22 @@ def test_rmat_s20_vertex_sampling():
     og = oracle.load(n, lo, hi, p)
     oest, _ = og.sample_vertices(ts, 1000, 8, 2026)
     assert np.array_equal(est, oest)
+
+
+def test_rmat_s20_sign_worlds():
+    n, lo, hi = inputs.rmat_graph(20, seed=1)
+    p = inputs.draw_p(lo.shape[0], "beta22", 2)
+    say("rmat20 sign worlds m_in", lo.shape[0])
+    g = device_graph(n, lo, hi, p)
+    E = g.expected()
+    many = g.sign_worlds(1024, 7).cpu().numpy().astype(np.float64)
+    assert abs(many.mean() - E) <= 4 * many.std(ddof=1) / np.sqrt(1024), (many.mean(), E)
+    few = g.sign_worlds(32, 8).cpu().numpy()
+    del g
+    torch.cuda.empty_cache()
+    say("oracle load")
+    og = oracle.load(n, lo, hi, p)
+    assert np.array_equal(few, og.sign_worlds(32, 8))
 
 
 def test_rmat_s23_count_and_sampled_edge_locals():

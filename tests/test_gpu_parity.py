@@ -372,6 +372,35 @@ def test_topk_edge_cases():
         assert ei.value.code == utri.UTRI_E_INVALID
 
 
+@pytest.mark.parametrize("ci", [0, 3, 4, 6])
+def test_sign_worlds_match_oracle(ci):
+    name, n, lo, hi = CASES[ci]
+    for dist, W, seed in [("uniform", 1024, 11), ("beta0505", 32, 12), ("half", 64, 13),
+                          ("certain", 256, 14)]:
+        p = inputs.draw_p(lo.shape[0], dist, 81 + ci)
+        og = oracle.load(n, lo, hi, p)
+        g = gpu_graph(n, lo, hi, p)
+        say("sign worlds", name, dist, W)
+        got = g.sign_worlds(W, seed).cpu().numpy()
+        assert np.array_equal(got, og.sign_worlds(W, seed)), (name, dist, W)
+
+
+def test_sign_worlds_counter_flushes(monkeypatch):
+    # counters flushed every 3 additions instead of before 2^16: same totals
+    n, lo, hi = inputs.rmat_graph(13, seed=9)
+    p = inputs.draw_p(lo.shape[0], "uniform", 3)
+    og = oracle.load(n, lo, hi, p)
+    want = og.sign_worlds(512, 5)
+    monkeypatch.setenv("UTRI_SIGN_FLUSH", "3")
+    g = gpu_graph(n, lo, hi, p)
+    say("sign worlds flushes")
+    assert np.array_equal(g.sign_worlds(512, 5).cpu().numpy(), want)
+    for bad in (0, 16, 48, 2048):
+        with pytest.raises(utri.UtriError) as ei:
+            g.sign_worlds(bad, 5)
+        assert ei.value.code == utri.UTRI_E_INVALID
+
+
 def test_batch_eager_and_graph_replays():
     n, lo, hi = inputs.rmat_graph(13, seed=9)
     p = inputs.draw_p(lo.shape[0], "beta22", 2)
