@@ -401,6 +401,25 @@ def test_sign_worlds_counter_flushes(monkeypatch):
         assert ei.value.code == utri.UTRI_E_INVALID
 
 
+def test_sweeps_quick(tmp_path):
+    """The experiment sweeps run end to end on small graphs; every row is well formed."""
+    from paper_2602_14084_amd import sweeps
+    out = tmp_path / "sw.json"
+    say("sweeps quick")
+    sweeps.main(["--quick", "--out", str(out)])
+    import json
+    res = json.loads(out.read_text())
+    ex = res["exact_rmat_s12_beta22"]
+    assert [r["t"] for r in ex] == sweeps.TS
+    assert all(r["plain_ms"] > 0 and r["pruned_ms"] > 0 for r in ex)
+    # counts fall as t grows (the candidate sets are nested)
+    cb = [r["counts"][0] for r in ex]
+    assert all(a >= b for a, b in zip(cb, cb[1:]))
+    assert set(res["distributions_rmat_s12"]) == set(sweeps.DISTS)
+    m = res["mape_rmat_s12_beta22"]
+    assert len(m["edge"]) == 4 and len(m["vertex"]) == 4
+
+
 def test_batch_eager_and_graph_replays():
     n, lo, hi = inputs.rmat_graph(13, seed=9)
     p = inputs.draw_p(lo.shape[0], "beta22", 2)
