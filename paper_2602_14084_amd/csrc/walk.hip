@@ -110,6 +110,7 @@ constexpr int SIGN_Q = 128;  // triangles queued per wave
 
 struct WalkLaneState {
     uint64_t nb = 0, nu = 0;       // COUNT / ENUM_COUNT
+    uint32_t nb32 = 0, nu32 = 0;   // COUNT / ENUM_COUNT within one item (added to nb / nu)
     uint64_t tri = 0;              // EXPECTED / STATS
     uint64_t slo = 0;              // EXPECTED: sum of low 32 bits of each fixed-point term
     int64_t shi = 0;               // EXPECTED: sum of the terms shifted right by 32
@@ -297,8 +298,9 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
                         }
                     }
                     if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) {
-                        st.nb += (dec == 1) ? 1u : 0u;
-                        st.nu += (dec == 2) ? 1u : 0u;
+                        // dec is 0, 1 or 2 here: bit 0 counts balanced, bit 1 unbalanced
+                        st.nb32 += (uint32_t)dec & 1u;
+                        st.nu32 += (uint32_t)dec >> 1;
                     } else if (MODE == WALK_ENUM_FILL) {
                         is_b = (dec == 1) && (wp.which & UTRI_BAL);
                         is_u = (dec == 2) && (wp.which & UTRI_UNBAL);
@@ -440,6 +442,10 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
                              pv, crs, H, st, run_b, run_u);
         }
     }
+    // an item counts at most its candidates per lane, far below 2^32
+    st.nb += st.nb32;
+    st.nu += st.nu32;
+    st.nb32 = st.nu32 = 0;
     if (MODE == WALK_ENUM_COUNT) {
         const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
         if (lane == 0) { wp.cnt_b[it] = (int64_t)nb; wp.cnt_u[it] = (int64_t)nu; }
@@ -497,6 +503,10 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
                              pv, crs, H, st, run_b, run_u);
         }
     }
+    // an item counts at most its candidates per lane, far below 2^32
+    st.nb += st.nb32;
+    st.nu += st.nu32;
+    st.nb32 = st.nu32 = 0;
     if (MODE == WALK_ENUM_COUNT) {
         const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
         if (lane == 0) { wp.cnt_b[slot] = (int64_t)nb; wp.cnt_u[slot] = (int64_t)nu; }
