@@ -375,6 +375,12 @@ def test_sign_convention():
         x = oracle.philox4x32_10([e, w // 4, 1, 0], [seed & 0xFFFFFFFF, seed >> 32])
         pos = F(int(x[w % 4])) < F(p) * 2 ** 32
         assert oracle.sign_negative(seed, e, w, p) == (0 if pos else 1)
+    # the comparison is strict: P+ = u / 2^32 exactly makes the edge negative
+    for seed, e, w in [(77, 5, 9), (2 ** 40 + 3, 123, 1022)]:
+        x = oracle.philox4x32_10([e, w // 4, 1, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        u = int(x[w % 4])
+        assert oracle.sign_negative(seed, e, w, u / 2 ** 32) == 1
+        assert oracle.sign_negative(seed, e, w, (u + 1) / 2 ** 32) == 0
     # frequency of positive signs matches P+ (binomial, 4 sigma)
     for p in (0.1, 0.5, 0.77):
         k = sum(1 - oracle.sign_negative(3, e, q, p) for e in range(40) for q in range(100))
