@@ -66,8 +66,11 @@ enum { UTRI_BAL = 1, UTRI_UNBAL = 2, UTRI_BOTH = 3 };
 /* Pointer kinds for inputs / outputs that may live on either side. */
 enum { UTRI_HOST_PTR = 0, UTRI_DEVICE_PTR = 1 };
 
-/* Sampling schemes: edge sampling (Section 6.2) and vertex sampling (Section 6.1). */
-enum { UTRI_SAMPLE_EDGE = 0, UTRI_SAMPLE_VERTEX = 1 };
+/* Sampling schemes: edge sampling (Section 6.2) and vertex sampling (Section 6.1) with the
+ * improved local searches, and the same estimators with the baseline local search (no
+ * Lemma-2 pruning: every neighbour is searched), which give identical estimates. */
+enum { UTRI_SAMPLE_EDGE = 0, UTRI_SAMPLE_VERTEX = 1, UTRI_SAMPLE_EDGE_PLAIN = 2,
+       UTRI_SAMPLE_VERTEX_PLAIN = 3 };
 
 /*
  * Build a graph handle (Definition "Uncertain Signed Graph", Section 3).
@@ -205,7 +208,9 @@ int utri_topk(utri_graph* g, int64_t k, int which, int32_t* tri, double* s, int6
  *    plain vertex local count of utri_vertex_local): range n, est = n * (sum of vertex
  *    local counts) / (3k). Needs one host synchronisation to size its edge records.
  * est: device FP64 [worlds][nt][2], computed as ((double)sum * (double)range) /
- * (3.0 * (double)k). Errors: UTRI_E_INVALID for another scheme, k <= 0, worlds <= 0, or
+ * (3.0 * (double)k). UTRI_SAMPLE_EDGE_PLAIN / UTRI_SAMPLE_VERTEX_PLAIN run the same
+ * draws with the baseline local search (the paper's eBase / vBase), for comparison.
+ * Errors: UTRI_E_INVALID for another scheme, k <= 0, worlds <= 0, or
  * an empty range (m = 0 for edges, n = 0 for vertices).
  */
 int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,

@@ -627,6 +627,10 @@ int utri_topk(utri_graph* g, int64_t k, int which, int32_t* tri, double* sv, int
 int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds, uint64_t seed,
                 int scheme, double* est, void* hip_stream) {
     UTRI_TRY(check_graph(g));
+    // the baseline schemes are the same estimators without the Lemma-2 pruning of the
+    // local search: full rows are searched and every drawn edge is searched
+    const bool plain = scheme == UTRI_SAMPLE_EDGE_PLAIN || scheme == UTRI_SAMPLE_VERTEX_PLAIN;
+    if (plain) scheme = scheme == UTRI_SAMPLE_EDGE_PLAIN ? UTRI_SAMPLE_EDGE : UTRI_SAMPLE_VERTEX;
     if ((scheme != UTRI_SAMPLE_EDGE && scheme != UTRI_SAMPLE_VERTEX) || k <= 0 || worlds <= 0 || !est)
         return UTRI_E_INVALID;
     if (scheme == UTRI_SAMPLE_EDGE ? g->m == 0 : g->n == 0) return UTRI_E_INVALID;
@@ -637,8 +641,9 @@ int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t world
     double* dc;
     int32_t* dord;
     UTRI_TRY(upload_thresholds(g, cv, order, s, &dc, &dord));
+    const double cprune = plain ? 0.0 : cv[0];
     int32_t* slen;
-    UTRI_TRY(utri_sym_prepare(g, cv[0], s, &slen));
+    UTRI_TRY(utri_sym_prepare(g, cprune, s, &slen));
     const size_t nh = (size_t)worlds * 2 * (nt + 1);
     void* hs;
     UTRI_TRY(utri_scratch(g, SCR_HIST, sizeof(uint64_t) * nh, &hs));
@@ -646,7 +651,7 @@ int utri_sample(utri_graph* g, const double* t, int nt, int64_t k, int32_t world
     SampleParams sp;
     sp.cvals = dc;
     sp.nt = nt;
-    sp.cmin = cv[0];
+    sp.cmin = cprune;
     sp.seed = seed;
     sp.k = k;
     sp.worlds = worlds;

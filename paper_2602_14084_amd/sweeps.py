@@ -9,7 +9,8 @@
   Beta(3, 1) and Beta(1, 3); improved runtime as t grows. The paper does not give the
   Normal's parameters; these are the generator's.
 * Sampling queries per second as t grows (the "queries per second" figures): edge and
-  vertex sampling with 1,024 independent runs of 10,000 (edge) / 1,000 (vertex) draws.
+  vertex sampling with 1,024 independent runs of 10,000 (edge) / 1,000 (vertex) draws,
+  with the improved local search and with the baseline one (eBase / vBase: no Lemma 2).
 * MAPE against the exact count as the number of samples grows, t = 0.8, averaged over 100
   runs (the "MAPE" figure): edge and vertex sampling, k = 10^2 ... 10^5.
 
@@ -84,7 +85,9 @@ def sampling_qps(torch, g, ts, worlds, k_edge, k_vertex):
     for t in ts:
         r = {"t": t}
         for name, scheme, k in (("edge", utri.UTRI_SAMPLE_EDGE, k_edge),
-                                ("vertex", utri.UTRI_SAMPLE_VERTEX, k_vertex)):
+                                ("vertex", utri.UTRI_SAMPLE_VERTEX, k_vertex),
+                                ("edge_base", utri.UTRI_SAMPLE_EDGE_PLAIN, k_edge),
+                                ("vertex_base", utri.UTRI_SAMPLE_VERTEX_PLAIN, k_vertex)):
             g.sample([t], k, worlds, 11, scheme)
             ms = _ms(torch, lambda: g.sample([t], k, worlds, 11, scheme))
             r[name + "_ms"] = ms

@@ -29,7 +29,7 @@ UTRI_E_RANGE = -6
 UTRI_PLAIN, UTRI_PRUNED, UTRI_PRUNED_L3 = 0, 1, 2
 UTRI_BAL, UTRI_UNBAL, UTRI_BOTH = 1, 2, 3
 UTRI_HOST_PTR, UTRI_DEVICE_PTR = 0, 1
-UTRI_SAMPLE_EDGE, UTRI_SAMPLE_VERTEX = 0, 1
+UTRI_SAMPLE_EDGE, UTRI_SAMPLE_VERTEX, UTRI_SAMPLE_EDGE_PLAIN, UTRI_SAMPLE_VERTEX_PLAIN = 0, 1, 2, 3
 
 ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",

@@ -307,6 +307,21 @@ def test_vertex_sampler_groups_and_passes(monkeypatch):
     assert np.array_equal(g2.sample(ts, k, W, seed, utri.UTRI_SAMPLE_VERTEX).cpu().numpy(), want)
 
 
+def test_baseline_local_search_gives_identical_estimates():
+    # the Lemma-2 pruning only skips unclassifiable triangles, so the baseline local search
+    # (full rows) must give the same estimates bit for bit
+    n, lo, hi = inputs.rmat_graph(13, seed=9)
+    p = inputs.draw_p(lo.shape[0], "beta22", 2)
+    g = gpu_graph(n, lo, hi, p)
+    ts = [0.55, 0.8, 0.7]
+    for imp, base in ((utri.UTRI_SAMPLE_EDGE, utri.UTRI_SAMPLE_EDGE_PLAIN),
+                      (utri.UTRI_SAMPLE_VERTEX, utri.UTRI_SAMPLE_VERTEX_PLAIN)):
+        say("baseline local search", base)
+        a = g.sample(ts, 300, 9, 4, imp).cpu().numpy()
+        b = g.sample(ts, 300, 9, 4, base).cpu().numpy()
+        assert np.array_equal(a, b)
+
+
 def test_vertex_sampler_edge_cases():
     # a graph with edges but no triangle, and one with isolated vertices only
     lo = np.array([0, 1, 2], np.int64)
