@@ -574,10 +574,12 @@ int utri_topk(utri_graph* g, int64_t k, int which, int32_t* tri, double* sv, int
     // tried from t = 1 down, so the walks prune as much as the answer allows (Lemma 2)
     std::vector<double> ts;
     std::vector<int64_t> cnt;
-    const double starts[3] = {0.95, 0.8, 0.5};
+    // bands [0.999, 1], [0.99, 0.999], [0.9, 0.99], [0.5, 0.9]: each walk costs what its
+    // lowest threshold prunes, so the answer's own band dominates the total
+    const double starts[4] = {0.999, 0.99, 0.9, 0.5};
     double lo = 0.5, hi = 1.0;
     bool found = false;
-    for (int b = 0; b < 3 && !found; b++) {
+    for (int b = 0; b < 4 && !found; b++) {
         lo = starts[b];
         hi = b == 0 ? 1.0 : starts[b - 1];
         UTRI_TRY(count_ladder(g, lo, hi, cls, ts, cnt, hip_stream));
