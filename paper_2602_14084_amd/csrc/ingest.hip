@@ -99,13 +99,22 @@ __global__ void k_iota_u32(uint32_t* __restrict__ a, int64_t n) {
     if (i < n) a[i] = (uint32_t)i;
 }
 
-__global__ void k_copy_deg_u32(const int32_t* __restrict__ deg, uint32_t* __restrict__ key,
-                               int64_t n) {
+// Node-Order sort key of vertex i: degree first; ties by a fixed bijective mix of the id
+// (the finaliser of MurmurHash3), so that within a degree class the new ids are in no
+// input-dependent pattern and their low bits index the walk's LDS tables directly.
+__global__ void k_rank_key(const int32_t* __restrict__ deg, uint64_t* __restrict__ key, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) key[i] = (uint32_t)deg[i];
+    if (i >= n) return;
+    uint32_t x = (uint32_t)i;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    key[i] = ((uint64_t)(uint32_t)deg[i] << 32) | x;
 }
 
-__global__ void k_relabel(const uint32_t* __restrict__ order, const uint32_t* __restrict__ sdeg,
+__global__ void k_relabel(const uint32_t* __restrict__ order, const uint64_t* __restrict__ skey,
                           int64_t n, int32_t* __restrict__ perm, int32_t* __restrict__ inv,
                           int32_t* __restrict__ deg_new) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,7 +122,7 @@ __global__ void k_relabel(const uint32_t* __restrict__ order, const uint32_t* __
     uint32_t old = order[i];
     perm[i] = (int32_t)old;
     inv[old] = (int32_t)i;
-    deg_new[i] = (int32_t)sdeg[i];
+    deg_new[i] = (int32_t)(skey[i] >> 32);
 }
 
 __global__ void k_max_i32(const int32_t* __restrict__ a, int64_t n, unsigned int* __restrict__ out) {
@@ -533,14 +542,15 @@ static int load_impl(const int64_t* src, const int64_t* dst, const double* p, in
                            pos, m_in, g->e_lo, g->e_hi, g->e_p, g->e_d);
         UTRI_HIP_TRY(hipGetLastError());
     }
-    // degrees and Node-Order relabelling (stable sort by degree keeps ids ascending)
+    // degrees and Node-Order relabelling (by degree, ties by the mixed id)
     UTRI_TRY(dev_alloc(&g->perm, n));
     UTRI_TRY(dev_alloc(&g->inv, n));
     UTRI_TRY(dev_alloc(&g->deg_new, n));
     if (n > 0) {
         TmpBuf bdeg, bdk, bdk2, bo1, bo2;
         int32_t* deg;
-        uint32_t *dk, *dk2, *o1, *o2;
+        uint64_t *dk, *dk2;
+        uint32_t *o1, *o2;
         UTRI_TRY(tmp_alloc(bdeg, n, &deg));
         UTRI_TRY(tmp_alloc(bdk, n, &dk));
         UTRI_TRY(tmp_alloc(bdk2, n, &dk2));
@@ -552,7 +562,7 @@ static int load_impl(const int64_t* src, const int64_t* dst, const double* p, in
         }
         unsigned int* dmax = (unsigned int*)(g->d_flags + 1);
         hipLaunchKernelGGL(k_max_i32, dim3(blocks_for(n)), dim3(TPB), 0, s, deg, n, dmax);
-        hipLaunchKernelGGL(k_copy_deg_u32, dim3(blocks_for(n)), dim3(TPB), 0, s, deg, dk, n);
+        hipLaunchKernelGGL(k_rank_key, dim3(blocks_for(n)), dim3(TPB), 0, s, deg, dk, n);
         hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(n)), dim3(TPB), 0, s, o1, n);
         UTRI_HIP_TRY(hipGetLastError());
         uint32_t md = 0;
@@ -560,7 +570,7 @@ static int load_impl(const int64_t* src, const int64_t* dst, const double* p, in
         UTRI_HIP_TRY(hipStreamSynchronize(s));
         g->max_deg = md;
         unsigned dbits = bitlen(md) ? bitlen(md) : 1;
-        UTRI_TRY(sort_pairs(g, dk, dk2, o1, o2, n, dbits, s));
+        UTRI_TRY(sort_pairs(g, dk, dk2, o1, o2, n, 32u + dbits, s));
         hipLaunchKernelGGL(k_relabel, dim3(blocks_for(n)), dim3(TPB), 0, s, o2, dk2, n, g->perm,
                            g->inv, g->deg_new);
         UTRI_HIP_TRY(hipGetLastError());

@@ -3,7 +3,9 @@
 // Data layout in HBM (all device memory, owned by the graph handle):
 //   canonical edges, edge-id order      e_lo/e_hi int32 [m], e_p/e_d f64 [m]
 //   vertex relabelling                  perm (new -> original) / inv int32 [n]
-//       new ids rank vertices by (degree, id): the Node Order of Section 4.
+//       new ids rank vertices by degree, ties by a fixed bijective mix of the id: the
+//       Node Order of Section 4 with another tie-break (any strict order by degree
+//       visits each triangle once).
 //   symmetric rows, new ids             s_off int64 [n+1], s_adj int32 [2m],
 //       each row in Absolute Edge Order  s_d f64 [2m], s_eid int32 [2m]
 //       (|d| descending, then neighbour id ascending; Section 5), so the entries

@@ -24,20 +24,12 @@ static_assert((CAP & (CAP - 1)) == 0 && (SLOTS & (SLOTS - 1)) == 0 && SLOTS * CA
               "table sizes are powers of two");
 constexpr int NB = 65;         // histogram bins (nt + 1 <= 65)
 
-#ifndef UTRI_WALK_HASH24
-#define UTRI_WALK_HASH24 0         // 1: full-rate 24-bit multiplicative hash; 0: 32-bit
-#endif
-
-// bucket of w in a table of 2^lg buckets (lg >= 1)
+// Bucket of w in a table of 2^lg buckets (lg >= 1): its low bits. Vertex ids are ranks in
+// (degree, mixed id) order, so within a degree class they follow no input pattern, and the
+// few vertices of distinct high degrees have consecutive ids, which land in distinct
+// buckets; a multiplicative hash would cost two more instructions per probe.
 __device__ __forceinline__ uint32_t walk_hash(int32_t w, int lg) {
-#if UTRI_WALK_HASH24
-    // the 24-bit multiplier runs at full rate (the 32-bit one at quarter rate); ids above
-    // 2^24 fold their high bits in. __umul24 returns a signed int: shift the unsigned value
-    const uint32_t x = (uint32_t)w ^ ((uint32_t)w >> 24);
-    return (uint32_t)__umul24(x, 0x9E3779u) >> (32 - lg);
-#else
-    return utri_hash32(w, lg);
-#endif
+    return (uint32_t)w & ((1u << lg) - 1u);
 }
 
 // Stage `cl` source entries starting at o_adj[base] into an open-addressing table of
