@@ -435,6 +435,25 @@ def test_sweeps_quick(tmp_path):
     assert len(m["edge"]) == 4 and len(m["vertex"]) == 4
 
 
+def test_autotune_keeps_results_and_caches(monkeypatch, tmp_path):
+    # tuning only picks launch shapes: every result stays the oracle's; the choice is
+    # written to the cache and a later handle of the same graph reads it back
+    n, lo, hi = inputs.rmat_graph(12, seed=3)
+    p = inputs.draw_p(lo.shape[0], "uniform", 21)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    cache = tmp_path / "tune.jsonl"
+    say("autotune rmat12")
+    g.autotune(0.7, str(cache))
+    assert g.count(0.7) == tuple(og.count(0.7))
+    assert np.array_equal(g.sample([0.7], 500, 4, 3).cpu().numpy(), og.sample([0.7], 500, 4, 3)[0])
+    text = cache.read_text()
+    assert "walk_blocks_per_cu" in text and "sample_chunk" in text
+    monkeypatch.setenv("UTRI_TUNE_CACHE", str(cache))
+    g2 = gpu_graph(n, lo, hi, p)
+    assert g2.count(0.8) == tuple(og.count(0.8))
+
+
 def test_batch_eager_and_graph_replays():
     n, lo, hi = inputs.rmat_graph(13, seed=9)
     p = inputs.draw_p(lo.shape[0], "beta22", 2)
