@@ -62,7 +62,7 @@ enum : uint32_t {
 // scratch buffers kept by a handle between calls (grown on demand)
 enum UtriScratch {
     SCR_TEMP = 0,     // rocPRIM temporary storage
-    SCR_LEN,          // int32 [n] row prefix lengths at c (oriented)
+    SCR_LEN,          // int32 [2n+2] row prefix lengths at c (oriented, then symmetric)
     SCR_SLEN,         // int32 [n] row prefix lengths at c (symmetric)
     SCR_ICNT,         // int32 [n] items per vertex
     SCR_IOFF,         // int64 [n] item offsets
@@ -391,6 +391,13 @@ struct WalkParams {
     int ww = 0;
     unsigned long long* wcount = nullptr;
     uint32_t sign_flush_at = 65535;  // additions between counter flushes (<= 2^16 - 1)
+    // symmetric rows: the partner lists of the walk items (set at launch), and the kept
+    // prefix length of each vertex's symmetric row
+    const int64_t* s_off = nullptr;
+    const int32_t* s_adj = nullptr;
+    const double* s_d = nullptr;
+    const int32_t* s_eid = nullptr;
+    const int32_t* slen = nullptr;
 };
 
 // Negative-sign masks of `ww` words per edge (worlds 32 ww) for the sign-world walk.

@@ -51,6 +51,13 @@ constexpr int HSH = SLOTSH * CAPH;    // work-group table slots (buckets of 4)
 #ifndef UTRI_WALK_DYNAMIC
 #define UTRI_WALK_DYNAMIC 1        // 1: items handed out by atomic work queues; 0: static stride
 #endif
+#ifndef UTRI_WALK_PR
+#define UTRI_WALK_PR 1024          // symmetric-row entries (partners) per item
+#endif
+constexpr int PR = UTRI_WALK_PR;
+#ifndef UTRI_WALK_SHORTER
+#define UTRI_WALK_SHORTER 1        // 1: each edge streams the shorter kept row; 0: always N+(v)
+#endif
 
 
 inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
@@ -68,41 +75,89 @@ static_assert(CAPH >= CAP && CAPH <= 65536 && (CAPH & (CAPH - 1)) == 0 &&
                   (SLOTSH & (SLOTSH - 1)) == 0,
               "work-group chunks hold every long row's chunk; table sizes are powers of two");
 
-// Bounds of the two item lists: light items (one per source row with 2 <= len <= CAP)
-// and heavy items (len > CAP, ceil(len / CAPH) chunks per row).
-inline int64_t light_bound(const utri_graph* g) { return std::min<int64_t>(g->n, g->m / 2) + 1; }
-inline int64_t heavy_bound(const utri_graph* g) { return 2 * (g->m / CAP) + 2; }
+// Items. Every vertex x with a kept oriented row of len >= 2 stages (chunks of) N+(x) as a
+// table and streams, for each partner y (a kept neighbour of x, in ranges of PR entries of
+// the symmetric row), the kept row N+(y) through it. Each kept edge {x, y} is streamed
+// from exactly one side: the shorter kept row goes through the longer one's table (ties:
+// the row of the higher-ranked end through the lower one's table, as in the plain forward
+// iteration). Either way w runs over N+(u) ∩ N+(v) for the oriented edge u -> v, so the
+// triangles visited are those of Section 4, once each. Item word: vertex in bits 0-30,
+// table chunk in bits 32-42, partner range in bits 43-63.
+//   light items: 2 <= len <= CAP, one per partner range;
+//   heavy items: len > CAP, one per (chunk of CAPH entries, partner range).
+__host__ __device__ inline int64_t item_word(int64_t v, int64_t chunk, int64_t range) {
+    return (int64_t)(((uint64_t)range << 43) | ((uint64_t)chunk << 32) | (uint64_t)v);
+}
+__device__ inline int item_vertex(int64_t it) { return (int)(it & 0x7FFFFFFF); }
+__device__ inline int item_chunk(int64_t it) { return (int)(((uint64_t)it >> 32) & 0x7FF); }
+__device__ inline int item_range(int64_t it) { return (int)((uint64_t)it >> 43); }
+constexpr int64_t MAX_CHUNKS = 2048;
+__host__ __device__ inline int partner_ranges(int32_t sl) { return sl > PR ? (sl + PR - 1) / PR : 1; }
 
+// Bounds of the two item lists (a kept symmetric row of sl entries has at most
+// 1 + sl / PR ranges; the symmetric rows hold 2m entries).
+inline int64_t chunks_bound(const utri_graph* g) { return (g->max_out + CAPH - 1) / CAPH + 1; }
+inline int64_t light_bound(const utri_graph* g) {
+    return std::min<int64_t>(g->n, g->m / 2) + 2 * g->m / PR + 1;
+}
+inline int64_t heavy_bound(const utri_graph* g) {
+    return g->m / CAPH + g->m / CAP + chunks_bound(g) * (g->m / CAP + 2 * g->m / PR + 1) + 2;
+}
+
+// Kept prefixes at c of the oriented row (len) and of the symmetric row (slen) of each
+// vertex, and its light and heavy item counts.
 __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restrict__ dd,
+                         const int64_t* __restrict__ soff, const double* __restrict__ sd,
                          int64_t n, double c, int32_t* __restrict__ len,
-                         int32_t* __restrict__ lcnt, int32_t* __restrict__ hcnt) {
+                         int32_t* __restrict__ slen, int32_t* __restrict__ lcnt,
+                         int32_t* __restrict__ hcnt) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    int64_t a = off[v], b = off[v + 1];
-    int64_t lo = a, hi = b;
-    if (c > 0.0) {
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (fabs(dd[mid]) >= c) lo = mid + 1; else hi = mid;
+    int32_t L, SL;
+    {
+        int64_t a = off[v], b = off[v + 1], lo = a, hi = b;
+        if (c > 0.0) {
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (fabs(dd[mid]) >= c) lo = mid + 1; else hi = mid;
+            }
+        } else {
+            lo = b;
         }
-    } else {
-        lo = b;
+        L = (int32_t)(lo - a);
     }
-    const int32_t L = (int32_t)(lo - a);
+    {
+        int64_t a = soff[v], b = soff[v + 1], lo = a, hi = b;
+        if (c > 0.0) {
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (fabs(sd[mid]) >= c) lo = mid + 1; else hi = mid;
+            }
+        } else {
+            lo = b;
+        }
+        SL = (int32_t)(lo - a);
+    }
     len[v] = L;
-    lcnt[v] = (L >= 2 && L <= CAP) ? 1 : 0;
-    hcnt[v] = (L > CAP) ? (L + CAPH - 1) / CAPH : 0;
+    slen[v] = SL;
+    const int nr = partner_ranges(SL);
+    lcnt[v] = (L >= 2 && L <= CAP) ? nr : 0;
+    hcnt[v] = (L > CAP) ? ((L + CAPH - 1) / CAPH) * nr : 0;
 }
 
 __global__ void k_items(const int32_t* __restrict__ lcnt, const int32_t* __restrict__ hcnt,
-                        const int64_t* __restrict__ loff, const int64_t* __restrict__ hoff,
-                        int64_t n, int64_t hbase, int64_t* __restrict__ items) {
+                        const int32_t* __restrict__ slen, const int64_t* __restrict__ loff,
+                        const int64_t* __restrict__ hoff, int64_t n, int64_t hbase,
+                        int64_t* __restrict__ items) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    if (lcnt[v]) items[loff[v]] = v;
-    const int c = hcnt[v];
+    const int nl = lcnt[v];
+    for (int r = 0; r < nl; r++) items[loff[v] + r] = item_word(v, 0, r);
+    const int nh = hcnt[v];
+    if (nh == 0) return;
+    const int nr = partner_ranges(slen[v]);
     const int64_t o = hbase + hoff[v];
-    for (int k = 0; k < c; k++) items[o + k] = ((int64_t)k << 32) | (int64_t)v;
+    for (int k = 0; k < nh; k++) items[o + k] = item_word(v, k / nr, k % nr);
 }
 
 constexpr int SIGN_K = 16;   // bit planes of the sign-world counters (flush before 2^16)
@@ -371,46 +426,60 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* 
         stream_row<MODE, 1>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
 }
 
-// Load, on lane i, v = N+(u)[i0 + i] with its row start, kept length and d_uv.
-__device__ __forceinline__ void load_targets(const WalkParams& wp, const int64_t* __restrict__ o_off,
-                                             const int32_t* __restrict__ o_adj,
-                                             const double* __restrict__ o_d,
-                                             const int32_t* __restrict__ len, int64_t ou, int Lu,
-                                             int i0, double dmax_chunk, int& v, int64_t& ov,
-                                             int& lv, double& duv, CodeRow& cr) {
+// Load, on lane i, partner y = entry sb + i0 + i of the kept symmetric row of x (np
+// entries in this item's range) with the start of N+(y), the kept length of N+(y) this
+// item streams (0 when the edge {x, y} is streamed from y's side, see k_items), d_xy and
+// the edge id (sign worlds).
+template <int MODE>
+__device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_t* __restrict__ o_off,
+                                              const double* __restrict__ o_d,
+                                              const int32_t* __restrict__ len, int x, int Lx,
+                                              int64_t sb, int np, int i0, double dmax_chunk,
+                                              int& y, int64_t& oy, int& ly, double& dxy,
+                                              int32_t& exy, CodeRow& cr) {
     const int i = i0 + utri_lane();
-    lv = 0; v = 0; ov = 0; duv = 0.0;
+    ly = 0; y = 0; oy = 0; dxy = 0.0; exy = 0;
     cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.neg_a = false;
-    if (i < Lu) {
-        v = (int)((uint32_t)o_adj[ou + i] & wp.idmask);
-        duv = o_d[ou + i];
-        ov = o_off[v];
-        lv = len[v];
-        if (wp.lemma3 && lv > 0) {
-            // Lemma 3: keep w only if |d_vw| * (|d_uv| * max|d_uw|) >= c (with slack)
-            const double P = __dmul_rn(fabs(duv), dmax_chunk);
-            int a = 0, b = lv;
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (__dmul_rn(fabs(o_d[ov + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
+    if (i < np) {
+        y = wp.s_adj[sb + i];
+        const int L = len[y];
+        const bool mine = UTRI_WALK_SHORTER ? ((y > x) ? (L <= Lx) : (L < Lx)) : (y > x);
+        if (mine && L > 0) {
+            dxy = wp.s_d[sb + i];
+            oy = o_off[y];
+            ly = L;
+            if (wp.lemma3) {
+                // Lemma 3: keep w only if |d_yw| * (|d_xy| * max|d_xw|) >= c (with slack)
+                const double P = __dmul_rn(fabs(dxy), dmax_chunk);
+                int a = 0, b = ly;
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (__dmul_rn(fabs(o_d[oy + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
+                }
+                ly = a;
             }
-            lv = a;
+            cr = code_row(wp, dxy);
+            if (MODE == WALK_SIGN) exy = wp.s_eid[sb + i];
         }
-        cr = code_row(wp, duv);
     }
 }
 
 
 
-// Wave item: source row u with 2 <= len <= CAP, staged in the wave's own table.
+// Wave item: vertex u with 2 <= len <= CAP, N+(u) staged in the wave's own table, and
+// one range of its partners.
 template <int MODE>
 __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                               int u, int64_t it, WalkLds& L, HistLds* H, WalkLaneState& st) {
+                               int64_t item, int64_t it, WalkLds& L, HistLds* H, WalkLaneState& st) {
     const int lane = utri_lane();
+    const int u = item_vertex(item);
+    const int rg = item_range(item);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
+    const int64_t sb = wp.s_off[u] + (int64_t)rg * PR;
+    const int np = min(PR, wp.slen[u] - rg * PR);
     const int lg = table_lg(Lu, SLOTS);
     const int nbk = 1 << lg;  // buckets
     for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) L.key[i] = 0;
@@ -422,17 +491,17 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const double dmax_chunk = fabs(o_d[ou]);
     int64_t run_b = 0, run_u = 0;
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[it]; run_u = wp.off_u[it]; }
-    for (int i0 = 0; i0 < Lu; i0 += UTRI_WAVE) {
+    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE) {
         int v, lv;
         int64_t ov;
         double duv;
+        int32_t euv;
         CodeRow cr;
-        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv, cr);
-        const int euv = (MODE == WALK_SIGN && i0 + lane < Lu) ? wp.o_eid[ou + i0 + lane] : 0;
-        const int nv = min(UTRI_WAVE, Lu - i0);
-        for (int si = 0; si < nv; si++) {
+        load_partners<MODE>(wp, o_off, o_d, len, u, Lu, sb, np, i0, dmax_chunk, v, ov, lv, duv,
+                            euv, cr);
+        for (uint64_t act = __ballot(lv > 0); act != 0; act &= act - 1) {
+            const int si = (int)__builtin_ctzll(act);
             const int lvs = bcast_i32(lv, si);
-            if (lvs == 0) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
                                : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
@@ -464,10 +533,13 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
                                 WalkLaneState& st) {
     const int lane = utri_lane();
     const int wib = threadIdx.x / UTRI_WAVE;
-    const int u = (int)(item & 0xFFFFFFFF);
-    const int chunk = (int)(item >> 32);
+    const int u = item_vertex(item);
+    const int chunk = item_chunk(item);
+    const int rg = item_range(item);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
+    const int64_t sb = wp.s_off[u] + (int64_t)rg * PR;
+    const int np = min(PR, wp.slen[u] - rg * PR);
     const int cb = chunk * CAPH;
     const int cl = min(CAPH, Lu - cb);
     const int lg = table_lg(cl, SLOTSH);
@@ -483,17 +555,19 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     const int64_t slot = wp.lb + 4 * hq + wib;
     int64_t run_b = 0, run_u = 0;
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[slot]; run_u = wp.off_u[slot]; }
-    for (int i0 = 0; i0 < Lu; i0 += UTRI_WAVE) {
+    int turn = 0;  // the four waves take the streamed partners in turn
+    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE) {
         int v, lv;
         int64_t ov;
         double duv;
+        int32_t euv;
         CodeRow cr;
-        load_targets(wp, o_off, o_adj, o_d, len, ou, Lu, i0, dmax_chunk, v, ov, lv, duv, cr);
-        const int euv = (MODE == WALK_SIGN && i0 + lane < Lu) ? wp.o_eid[ou + i0 + lane] : 0;
-        const int nv = min(UTRI_WAVE, Lu - i0);
-        for (int si = wib; si < nv; si += WPB) {
+        load_partners<MODE>(wp, o_off, o_d, len, u, Lu, sb, np, i0, dmax_chunk, v, ov, lv, duv,
+                            euv, cr);
+        for (uint64_t act = __ballot(lv > 0); act != 0; act &= act - 1, turn++) {
+            if ((turn & (WPB - 1)) != wib) continue;
+            const int si = (int)__builtin_ctzll(act);
             const int lvs = bcast_i32(lv, si);
-            if (lvs == 0) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
                                : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
@@ -601,8 +675,8 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         const int64_t end = base + G < nl ? base + G : nl;
         for (int64_t q = base; q < end; q++) {
             const int64_t it = nl - 1 - q;
-            walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, (int)items[it], it,
-                                 S.wave[wib], H, st);
+            walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, S.wave[wib],
+                                 H, st);
         }
     }
 #else
@@ -616,7 +690,7 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
     const int64_t W = (int64_t)gridDim.x * WPB;
     for (int64_t q = gw; q < nl; q += W) {
         const int64_t it = nl - 1 - q;
-        walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, (int)items[it], it, S.wave[wib], H,
+        walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, S.wave[wib], H,
                              st);
     }
 #endif
@@ -687,7 +761,8 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     const int64_t n = g->n;
     const int64_t lb = light_bound(g), hb = heavy_bound(g);
     void *plen, *pcnt, *poff, *pitems, *pn;
-    UTRI_TRY(utri_scratch(g, SCR_LEN, sizeof(int32_t) * (size_t)(n + 1), &plen));
+    // oriented prefixes in [0, n], symmetric prefixes in [n + 1, 2n + 1]
+    UTRI_TRY(utri_scratch(g, SCR_LEN, sizeof(int32_t) * (size_t)(2 * n + 2), &plen));
     UTRI_TRY(utri_scratch(g, SCR_ICNT, sizeof(int32_t) * (size_t)(2 * n + 2), &pcnt));
     UTRI_TRY(utri_scratch(g, SCR_IOFF, sizeof(int64_t) * (size_t)(2 * n + 2), &poff));
     UTRI_TRY(utri_scratch(g, SCR_ITEMS, sizeof(int64_t) * (size_t)(lb + hb), &pitems));
@@ -701,21 +776,29 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     int32_t* hcnt = lcnt + n;
     int64_t* loff = (int64_t*)poff;
     int64_t* hoff = loff + n;
-    hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, n, c_rows,
-                       (int32_t*)plen, lcnt, hcnt);
+    if (chunks_bound(g) > MAX_CHUNKS) return UTRI_E_RANGE;  // the item word's chunk field
+    int32_t* slen = (int32_t*)plen + n + 1;
+    hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, g->s_off,
+                       g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt);
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
     UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
     hipLaunchKernelGGL(k_items, dim3(blocks_for(n)), dim3(TPB), 0, s, (const int32_t*)lcnt,
-                       (const int32_t*)hcnt, (const int64_t*)loff, (const int64_t*)hoff, n, lb,
-                       (int64_t*)pitems);
+                       (const int32_t*)hcnt, (const int32_t*)slen, (const int64_t*)loff,
+                       (const int64_t*)hoff, n, lb, (int64_t*)pitems);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }
 
-// Graph-dependent fields of a launch: enumeration slot base, row packing, FP32 bounds of c.
-static void set_launch_fields(utri_graph* g, WalkParams& wp) {
+// Graph-dependent fields of a launch: enumeration slot base, row packing, symmetric rows
+// and their kept prefixes (stored after the oriented ones), FP32 bounds of c.
+static void set_launch_fields(utri_graph* g, WalkParams& wp, const int32_t* len) {
     wp.lb = light_bound(g);
+    wp.s_off = g->s_off;
+    wp.s_adj = g->s_adj;
+    wp.s_d = g->s_d;
+    wp.s_eid = g->s_eid;
+    wp.slen = len ? len + g->n + 1 : nullptr;
     wp.idmask = g->idmask;
     wp.idbits = g->idbits;
     wp.mb = g->code_mb;
@@ -754,7 +837,7 @@ int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int
     (void)n_items_host_bound;
     if (g->n == 0 || g->m == 0) return UTRI_OK;
     WalkParams wp = wp_in;
-    set_launch_fields(g, wp);
+    set_launch_fields(g, wp, len);
     // the work-queue counters live after the two item counts and restart at every launch
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
@@ -778,7 +861,7 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     (void)n_items_bound;
     if (g->n == 0 || g->m == 0) return UTRI_OK;
     WalkParams wp = wp_in;
-    set_launch_fields(g, wp);
+    set_launch_fields(g, wp, len);
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
