@@ -46,7 +46,7 @@ constexpr int SLOTSH = UTRI_WALK_SLOTS_WG;  // work-group table slots per staged
 constexpr int HSH = SLOTSH * CAPH;    // work-group table slots (buckets of 4)
 
 #ifndef UTRI_WALK_UNR_MAX
-#define UTRI_WALK_UNR_MAX 4        // loads in flight per lane on long target rows
+#define UTRI_WALK_UNR_MAX 8        // loads in flight per lane on long streamed rows
 #endif
 #ifndef UTRI_WALK_DYNAMIC
 #define UTRI_WALK_DYNAMIC 1        // 1: items handed out by atomic work queues; 0: static stride
@@ -315,6 +315,8 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* 
             pw[k] = (j0 + k * UTRI_WAVE + lane < lvs) ? *(const uint32_t*)(lb + k * 4 * UTRI_WAVE) : 0u;
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
+            // strips past the row end hold no entries (wave-uniform exit)
+            if (k > 0 && j0 + k * UTRI_WAVE >= lvs) break;
             const int j = j0 + k * UTRI_WAVE + lane;
             const uint32_t w = pw[k] & wp.idmask;
             bool is_b = false, is_u = false;
