@@ -131,6 +131,8 @@ __device__ __forceinline__ void g_stream(const GradParams& P, const GTab& T, int
             pw[k] = (j0 + k * UTRI_WAVE + lane < lvs) ? *(const uint32_t*)(lb + k * 4 * UTRI_WAVE) : 0u;
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
+            // strips past the row end hold no entries (wave-uniform exit)
+            if (k > 0 && j0 + k * UTRI_WAVE >= lvs) break;
             const int j = j0 + k * UTRI_WAVE + lane;
             int h;
             const int kk = bucket_find(T.key, T.lg, T.mask, pw[k] & P.idmask, P.idmask, h);
