@@ -141,9 +141,11 @@ def main():
     assert again == counts, "counts differ between runs"
     teps = g.m / step_s
     stats = utri.utri_walk_stats(g.handle, args.tau, method)
-    # staged-source algorithmic bytes: 4 B per streamed target-row id, 12 B per kept
-    # source-row entry (id + d, read once), 8 B per candidate triangle (d_vw)
-    b_alg = 4 * stats["target_elems"] + 12 * stats["m_c"] + 8 * stats["candidates"]
+    # staged-table algorithmic bytes: 4 B per streamed row id (each kept edge streams the
+    # shorter of its two kept rows once), per kept edge 4 B of staged table id, 8 B of
+    # partner ids (it is listed in the symmetric rows of both ends) and 8 B of its d, and
+    # 8 B per candidate triangle (the streamed entry's d)
+    b_alg = 4 * stats["target_elems"] + 20 * stats["m_c"] + 8 * stats["candidates"]
     achieved = b_alg / (walk_ms / 1e3) / 1e9
     log(f"count {counts} step {step_s * 1e3:.2f} ms, walk kernel {walk_ms:.2f} ms, "
         f"TEPS {teps:.3e}, B_alg {b_alg / 1e9:.1f} GB -> {achieved:.0f} GB/s")

@@ -238,11 +238,12 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
 /*
  * Work figures of one counting walk at t (the units the cost analysis of Theorem 5.1,
  * Section 5, sums over): out (host int64 [5]) =
- *   [0] m_c: oriented edges kept (sum of the kept source-row prefixes),
- *   [1] sum over kept oriented edges u -> v of the kept target-row length of v,
- *   [2] candidate triangles (target-row entries found in the source row),
- *   [3] target-row entries actually streamed (rows longer than one work item are
- *       streamed once per item),
+ *   [0] m_c: oriented edges kept (sum of the kept oriented-row prefixes),
+ *   [1] sum over kept oriented edges u -> v of the kept length of the row the walk
+ *       streams for it: the shorter of N+(u) and N+(v) (N+(v) on ties),
+ *   [2] candidate triangles (streamed entries found in the staged row),
+ *   [3] row entries actually streamed (a row is streamed once per chunk of a staged
+ *       row longer than one work-group table),
  *   [4] work items. Waits for the stream.
  */
 int utri_walk_stats(utri_graph* g, double t, int method, int64_t out[5], void* hip_stream);

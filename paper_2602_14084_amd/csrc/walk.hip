@@ -5,21 +5,30 @@
 // is visited exactly once (Node Order, Section 4). Rows are stored in Absolute Edge
 // Order, so Lemma 2 (every triangle through an edge with |d| < c is unclassifiable)
 // reduces each row to a prefix of length len[x]; the optional Lemma-3 cut shortens the
-// target row N+(v) further, per pair, to entries with |d_vw| * |d_uv| * max|d_u.| >= c.
+// streamed row further, per pair, to the entries whose |d| times |d| of the pair's edge
+// times the largest |d| of the staged row (chunk) is at least c.
+//
+// Which row is streamed: for the oriented edge u -> v the triangles are the w in
+// N+(u) ∩ N+(v), and the intersection can be taken by staging either row as a hash table
+// and streaming the other through it. The walk streams the shorter kept row (ties: N+(v),
+// the plain forward iteration), which on R-MAT graphs streams well under half the ids of
+// always streaming N+(v). A work item is a vertex x with its kept row N+(x) staged and a
+// range of its kept symmetric row as partners y: y's row N+(y) is streamed through the
+// table when the edge {x, y} is streamed from x's side (see k_items).
 //
 // GPU mapping (persistent grid, two phases per work-group, atomic work queues):
-//   * long source rows (len > CAP = 128): one work-group per item (u, CAPH = 1024-entry
-//     chunk). The chunk of N+(u) is staged in a work-group LDS table and the four waves
-//     split the target rows N+(v) round-robin;
-//   * other source rows: one wave per item, the row staged in the wave's own table.
+//   * long staged rows (len > CAP = 128): one work-group per item (x, CAPH = 1024-entry
+//     chunk, partner range). The chunk of N+(x) is staged in a work-group LDS table and
+//     the four waves take the streamed partners in turn;
+//   * other staged rows: one wave per item, the row staged in the wave's own table.
 //   Tables are open addressing over buckets of four 32-bit keys, read with one 16-byte
 //   LDS load, at load factor 1/8 (wave) or 1/4 (work-group), so almost every probe ends
-//   in its home bucket. A target row N+(v) is streamed coalesced with v, its start and
-//   length broadcast in scalar registers; each lane loads up to four ids ahead (64
-//   apart) before probing them, so every wave keeps several loads in flight. Hits are
-//   classified from the d codes packed above the ids; only the few the codes leave
-//   undecided read d values. The classify, count, histogram, fixed-point, enumeration,
-//   sign-world and statistics epilogues are selected at compile time.
+//   in its home bucket. A streamed row is read coalesced, its start and length broadcast
+//   in scalar registers; each lane loads up to eight ids ahead (64 apart) before probing
+//   them, so every wave keeps several loads in flight. Hits are classified from the d
+//   codes packed above the ids; only the few the codes leave undecided read d values.
+//   The classify, count, histogram, fixed-point, enumeration, sign-world and statistics
+//   epilogues are selected at compile time.
 //
 // Sign worlds (possible-world Monte-Carlo of E): every triangle's three edge ids go to a
 // per-wave LDS queue; a full queue is drained with lanes over world words (world
