@@ -425,7 +425,9 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* 
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
 #if UTRI_WALK_UNR_MAX >= 8
-    if (lvs > 4 * UTRI_WAVE)
+    // the sign-world walk keeps its counter planes in registers: eight loads ahead would
+    // spill them
+    if (MODE != WALK_SIGN && lvs > 4 * UTRI_WAVE)
         stream_row<MODE, 8>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
     else
 #endif
