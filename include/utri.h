@@ -240,7 +240,8 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
  * Section 5, sums over): out (host int64 [5]) =
  *   [0] m_c: oriented edges kept (sum of the kept oriented-row prefixes),
  *   [1] sum over kept oriented edges u -> v of the kept length of the row the walk
- *       streams for it: the shorter of N+(u) and N+(v) (N+(v) on ties),
+ *       streams for it: the shorter of N+(u) and N+(v) (N+(v) on ties) when that pays
+ *       (the kept rows are long on average), else N+(v),
  *   [2] candidate triangles (streamed entries found in the staged row),
  *   [3] row entries actually streamed (a row is streamed once per chunk of a staged
  *       row longer than one work-group table),

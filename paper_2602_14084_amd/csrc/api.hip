@@ -223,7 +223,7 @@ int batch_sequence(utri_graph* g, const double* dc, const int32_t* dord, int nt,
     if (!items) {
         // no walk part: the kernel still needs a valid (zero) item count
         void* pn;
-        UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 4, &pn));
+        UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 6, &pn));
         nitems = (int64_t*)pn;
     }
     UTRI_TRY(utri_batch_launch(g, wp, items, nitems, len, 0, sp, slen, s));

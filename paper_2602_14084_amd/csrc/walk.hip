@@ -10,11 +10,12 @@
 //
 // Which row is streamed: for the oriented edge u -> v the triangles are the w in
 // N+(u) ∩ N+(v), and the intersection can be taken by staging either row as a hash table
-// and streaming the other through it. The walk streams the shorter kept row (ties: N+(v),
-// the plain forward iteration), which on R-MAT graphs streams well under half the ids of
-// always streaming N+(v). A work item is a vertex x with its kept row N+(x) staged and a
-// range of its kept symmetric row as partners y: y's row N+(y) is streamed through the
-// table when the edge {x, y} is streamed from x's side (see k_items).
+// and streaming the other through it. When the kept rows are long (see stream_shorter)
+// the walk streams the shorter kept row (ties: N+(v), the plain forward iteration), which
+// on R-MAT s23 streams 2.5x fewer ids than always streaming N+(v); otherwise it streams
+// N+(v). A work item is a vertex x with its kept row N+(x) staged and a range of its kept
+// symmetric row as partners y: y's row N+(y) is streamed through the table when the edge
+// {x, y} is streamed from x's side (see k_items).
 //
 // GPU mapping (persistent grid, two phases per work-group, atomic work queues):
 //   * long staged rows (len > CAP = 128): one work-group per item (x, CAPH = 1024-entry
@@ -103,6 +104,21 @@ __device__ inline int item_range(int64_t it) { return (int)((uint64_t)it >> 43);
 constexpr int64_t MAX_CHUNKS = 2048;
 __host__ __device__ inline int partner_ranges(int32_t sl) { return sl > PR ? (sl + PR - 1) / PR : 1; }
 
+// Streaming the shorter row pays when the rows the plain forward iteration streams are
+// long: it then skips most of their strips, while scanning both ends' symmetric rows for
+// partners costs about the same per edge either way. When the plain iteration would
+// stream fewer than UTRI_WALK_SHORTER_MIN ids per kept edge on average, and for the
+// sign-world walk (whose mask reads follow the staged row), items stream N+(v) for the v
+// of their own row (only the first partner range of an item has work then).
+#ifndef UTRI_WALK_SHORTER_MIN
+#define UTRI_WALK_SHORTER_MIN 320
+#endif
+template <int MODE>
+__device__ inline bool stream_shorter(const int64_t* n_items_dev) {
+    return UTRI_WALK_SHORTER && MODE != WALK_SIGN &&
+           (double)n_items_dev[5] >= (double)UTRI_WALK_SHORTER_MIN * (double)n_items_dev[4];
+}
+
 // Bounds of the two item lists (a kept symmetric row of sl entries has at most
 // 1 + sl / PR ranges; the symmetric rows hold 2m entries).
 inline int64_t chunks_bound(const utri_graph* g) { return (g->max_out + CAPH - 1) / CAPH + 1; }
@@ -114,39 +130,43 @@ inline int64_t heavy_bound(const utri_graph* g) {
 }
 
 // Kept prefixes at c of the oriented row (len) and of the symmetric row (slen) of each
-// vertex, and its light and heavy item counts.
+// vertex, and its light and heavy item counts. kept[0] += the kept oriented edges,
+// kept[1] += sum over v of (kept in-edges of v) * len(v): the ids the plain forward
+// iteration would stream.
+__device__ __forceinline__ int32_t kept_prefix(const int64_t* __restrict__ off,
+                                               const double* __restrict__ dd, int64_t v, double c) {
+    const int64_t a = off[v], b = off[v + 1];
+    int64_t lo = a, hi = b;
+    if (c > 0.0) {
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (fabs(dd[mid]) >= c) lo = mid + 1; else hi = mid;
+        }
+    } else {
+        lo = b;
+    }
+    return (int32_t)(lo - a);
+}
+
 __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restrict__ dd,
                          const int64_t* __restrict__ soff, const double* __restrict__ sd,
                          int64_t n, double c, int32_t* __restrict__ len,
                          int32_t* __restrict__ slen, int32_t* __restrict__ lcnt,
-                         int32_t* __restrict__ hcnt) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                         int32_t* __restrict__ hcnt, unsigned long long* __restrict__ kept) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t L = 0, SL = 0;
+    if (v < n) {
+        L = kept_prefix(off, dd, v, c);
+        SL = kept_prefix(soff, sd, v, c);
+    }
+    // one atomic per wave for each total
+    const uint64_t tl = utri_wave_sum_u64((uint64_t)L);
+    const uint64_t tw = utri_wave_sum_u64((uint64_t)(SL - L) * (uint64_t)L);
+    if (utri_lane() == 0) {
+        if (tl) atomicAdd(&kept[0], (unsigned long long)tl);
+        if (tw) atomicAdd(&kept[1], (unsigned long long)tw);
+    }
     if (v >= n) return;
-    int32_t L, SL;
-    {
-        int64_t a = off[v], b = off[v + 1], lo = a, hi = b;
-        if (c > 0.0) {
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if (fabs(dd[mid]) >= c) lo = mid + 1; else hi = mid;
-            }
-        } else {
-            lo = b;
-        }
-        L = (int32_t)(lo - a);
-    }
-    {
-        int64_t a = soff[v], b = soff[v + 1], lo = a, hi = b;
-        if (c > 0.0) {
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if (fabs(sd[mid]) >= c) lo = mid + 1; else hi = mid;
-            }
-        } else {
-            lo = b;
-        }
-        SL = (int32_t)(lo - a);
-    }
     len[v] = L;
     slen[v] = SL;
     const int nr = partner_ranges(SL);
@@ -445,20 +465,22 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* 
 // the edge id (sign worlds).
 template <int MODE>
 __device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_t* __restrict__ o_off,
+                                              const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
-                                              const int32_t* __restrict__ len, int x, int Lx,
-                                              int64_t sb, int np, int i0, double dmax_chunk,
-                                              int& y, int64_t& oy, int& ly, double& dxy,
-                                              int32_t& exy, CodeRow& cr) {
+                                              const int32_t* __restrict__ len, bool shorter, int x,
+                                              int Lx, int64_t sb, int np, int i0,
+                                              double dmax_chunk, int& y, int64_t& oy, int& ly,
+                                              double& dxy, int32_t& exy, CodeRow& cr) {
     const int i = i0 + utri_lane();
     ly = 0; y = 0; oy = 0; dxy = 0.0; exy = 0;
     cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.neg_a = false;
     if (i < np) {
-        y = wp.s_adj[sb + i];
+        // shorter: entry of x's kept symmetric row; else: entry of N+(x) itself
+        y = shorter ? wp.s_adj[sb + i] : (int)((uint32_t)o_adj[sb + i] & wp.idmask);
         const int L = len[y];
-        const bool mine = UTRI_WALK_SHORTER ? ((y > x) ? (L <= Lx) : (L < Lx)) : (y > x);
+        const bool mine = !shorter || ((y > x) ? (L <= Lx) : (L < Lx));
         if (mine && L > 0) {
-            dxy = wp.s_d[sb + i];
+            dxy = shorter ? wp.s_d[sb + i] : o_d[sb + i];
             oy = o_off[y];
             ly = L;
             if (wp.lemma3) {
@@ -472,7 +494,7 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_
                 ly = a;
             }
             cr = code_row(wp, dxy);
-            if (MODE == WALK_SIGN) exy = wp.s_eid[sb + i];
+            if (MODE == WALK_SIGN) exy = shorter ? wp.s_eid[sb + i] : wp.o_eid[sb + i];
         }
     }
 }
@@ -485,14 +507,16 @@ template <int MODE>
 __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                               int64_t item, int64_t it, WalkLds& L, HistLds* H, WalkLaneState& st) {
+                               int64_t item, int64_t it, bool shorter, WalkLds& L, HistLds* H,
+                               WalkLaneState& st) {
     const int lane = utri_lane();
     const int u = item_vertex(item);
     const int rg = item_range(item);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
-    const int64_t sb = wp.s_off[u] + (int64_t)rg * PR;
-    const int np = min(PR, wp.slen[u] - rg * PR);
+    const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * PR : ou;
+    const int np = shorter ? min(PR, wp.slen[u] - rg * PR) : (rg == 0 ? Lu : 0);
+    if (np <= 0) return;  // (the enumeration slots start zeroed)
     const int lg = table_lg(Lu, SLOTS);
     const int nbk = 1 << lg;  // buckets
     for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) L.key[i] = 0;
@@ -510,8 +534,8 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
         double duv;
         int32_t euv;
         CodeRow cr;
-        load_partners<MODE>(wp, o_off, o_d, len, u, Lu, sb, np, i0, dmax_chunk, v, ov, lv, duv,
-                            euv, cr);
+        load_partners<MODE>(wp, o_off, o_adj, o_d, len, shorter, u, Lu, sb, np, i0, dmax_chunk, v,
+                            ov, lv, duv, euv, cr);
         for (uint64_t act = __ballot(lv > 0); act != 0; act &= act - 1) {
             const int si = (int)__builtin_ctzll(act);
             const int lvs = bcast_i32(lv, si);
@@ -542,7 +566,7 @@ template <int MODE>
 __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                 const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                 const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                                int64_t item, int64_t hq, BlockLds& B, HistLds* H,
+                                int64_t item, int64_t hq, bool shorter, BlockLds& B, HistLds* H,
                                 WalkLaneState& st) {
     const int lane = utri_lane();
     const int wib = threadIdx.x / UTRI_WAVE;
@@ -551,8 +575,9 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     const int rg = item_range(item);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
-    const int64_t sb = wp.s_off[u] + (int64_t)rg * PR;
-    const int np = min(PR, wp.slen[u] - rg * PR);
+    const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * PR : ou;
+    const int np = shorter ? min(PR, wp.slen[u] - rg * PR) : (rg == 0 ? Lu : 0);
+    if (np <= 0) return;  // work-group uniform (the enumeration slots start zeroed)
     const int cb = chunk * CAPH;
     const int cl = min(CAPH, Lu - cb);
     const int lg = table_lg(cl, SLOTSH);
@@ -575,8 +600,8 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
         double duv;
         int32_t euv;
         CodeRow cr;
-        load_partners<MODE>(wp, o_off, o_d, len, u, Lu, sb, np, i0, dmax_chunk, v, ov, lv, duv,
-                            euv, cr);
+        load_partners<MODE>(wp, o_off, o_adj, o_d, len, shorter, u, Lu, sb, np, i0, dmax_chunk, v,
+                            ov, lv, duv, euv, cr);
         for (uint64_t act = __ballot(lv > 0); act != 0; act &= act - 1, turn++) {
             if ((turn & (WPB - 1)) != wib) continue;
             const int si = (int)__builtin_ctzll(act);
@@ -652,7 +677,7 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
                             const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                             const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
                             const int64_t* __restrict__ items, int64_t nl, int64_t nh,
-                            WalkShared& S, HistLds* H, WalkLaneState& st) {
+                            bool shorter, WalkShared& S, HistLds* H, WalkLaneState& st) {
     const int wib = threadIdx.x / UTRI_WAVE;
 #if UTRI_WALK_DYNAMIC
     // work queues: qctr[0] hands out heavy items to work-groups, qctr[1] light items to
@@ -665,8 +690,8 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         __syncthreads();
         if (q >= nh) break;
         const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, S.block,
-                              H, st);
+        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, shorter,
+                              S.block, H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
 #ifndef UTRI_WALK_QGROUP
@@ -688,23 +713,23 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         const int64_t end = base + G < nl ? base + G : nl;
         for (int64_t q = base; q < end; q++) {
             const int64_t it = nl - 1 - q;
-            walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, S.wave[wib],
-                                 H, st);
+            walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, shorter,
+                                 S.wave[wib], H, st);
         }
     }
 #else
     for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
         const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, S.block,
-                              H, st);
+        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, shorter,
+                              S.block, H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
     const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
     const int64_t W = (int64_t)gridDim.x * WPB;
     for (int64_t q = gw; q < nl; q += W) {
         const int64_t it = nl - 1 - q;
-        walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, S.wave[wib], H,
-                             st);
+        walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, shorter,
+                             S.wave[wib], H, st);
     }
 #endif
 }
@@ -726,7 +751,8 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
         thresh_stage(wp.cvals, wp.nt);
     }
     WalkLaneState st;
-    walk_phases<MODE>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0], n_items_dev[1], S,
+    walk_phases<MODE>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0], n_items_dev[1],
+                      stream_shorter<MODE>(n_items_dev), S,
                       H, st);
     walk_flush<MODE>(wp, o_d, H, st);
 }
@@ -759,7 +785,8 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
     WalkLaneState st;
     if (wp.acc != nullptr) {
         walk_phases<WALK_HIST>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                               n_items_dev[1], S.walk, H, st);
+                               n_items_dev[1], stream_shorter<WALK_HIST>(n_items_dev),
+                               S.walk, H, st);
         walk_flush<WALK_HIST>(wp, o_d, H, st);
     }
     __syncthreads();  // the walk's tables are no longer read; the sampler's reuse them
@@ -779,11 +806,13 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     UTRI_TRY(utri_scratch(g, SCR_ICNT, sizeof(int32_t) * (size_t)(2 * n + 2), &pcnt));
     UTRI_TRY(utri_scratch(g, SCR_IOFF, sizeof(int64_t) * (size_t)(2 * n + 2), &poff));
     UTRI_TRY(utri_scratch(g, SCR_ITEMS, sizeof(int64_t) * (size_t)(lb + hb), &pitems));
-    UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 4, &pn));
+    // [0] light items, [1] heavy items, [2..3] work-queue counters, [4] kept oriented
+    // edges, [5] ids the plain forward iteration would stream
+    UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 6, &pn));
     *items = (int64_t*)pitems;
     *n_items_dev = (int64_t*)pn;
     *len = (int32_t*)plen;
-    UTRI_TRY(utri_fill_u64(pn, 0, 4, s));
+    UTRI_TRY(utri_fill_u64(pn, 0, 6, s));
     if (n == 0) return UTRI_OK;
     int32_t* lcnt = (int32_t*)pcnt;
     int32_t* hcnt = lcnt + n;
@@ -792,7 +821,8 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     if (chunks_bound(g) > MAX_CHUNKS) return UTRI_E_RANGE;  // the item word's chunk field
     int32_t* slen = (int32_t*)plen + n + 1;
     hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, g->s_off,
-                       g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt);
+                       g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt,
+                       (unsigned long long*)pn + 4);  // [4], [5]
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
     UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
