@@ -463,11 +463,11 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* 
 // entries in this item's range) with the start of N+(y), the kept length of N+(y) this
 // item streams (0 when the edge {x, y} is streamed from y's side, see k_items), d_xy and
 // the edge id (sign worlds).
-template <int MODE>
+template <int MODE, bool shorter>
 __device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                               const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
-                                              const int32_t* __restrict__ len, bool shorter, int x,
+                                              const int32_t* __restrict__ len, int x,
                                               int Lx, int64_t sb, int np, int i0,
                                               double dmax_chunk, int& y, int64_t& oy, int& ly,
                                               double& dxy, int32_t& exy, CodeRow& cr) {
@@ -503,11 +503,11 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_
 
 // Wave item: vertex u with 2 <= len <= CAP, N+(u) staged in the wave's own table, and
 // one range of its partners.
-template <int MODE>
+template <int MODE, bool shorter>
 __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                               int64_t item, int64_t it, bool shorter, WalkLds& L, HistLds* H,
+                               int64_t item, int64_t it, WalkLds& L, HistLds* H,
                                WalkLaneState& st) {
     const int lane = utri_lane();
     const int u = item_vertex(item);
@@ -534,8 +534,8 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
         double duv;
         int32_t euv;
         CodeRow cr;
-        load_partners<MODE>(wp, o_off, o_adj, o_d, len, shorter, u, Lu, sb, np, i0, dmax_chunk, v,
-                            ov, lv, duv, euv, cr);
+        load_partners<MODE, shorter>(wp, o_off, o_adj, o_d, len, u, Lu, sb, np, i0, dmax_chunk,
+                                     v, ov, lv, duv, euv, cr);
         for (uint64_t act = __ballot(lv > 0); act != 0; act &= act - 1) {
             const int si = (int)__builtin_ctzll(act);
             const int lvs = bcast_i32(lv, si);
@@ -562,11 +562,11 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
 
 // Work-group item: chunk `chunk` (CAPH entries) of a long source row, one shared table,
 // target rows split round-robin over the four waves. Enumeration slots are per wave.
-template <int MODE>
+template <int MODE, bool shorter>
 __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                 const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                 const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                                int64_t item, int64_t hq, bool shorter, BlockLds& B, HistLds* H,
+                                int64_t item, int64_t hq, BlockLds& B, HistLds* H,
                                 WalkLaneState& st) {
     const int lane = utri_lane();
     const int wib = threadIdx.x / UTRI_WAVE;
@@ -600,8 +600,8 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
         double duv;
         int32_t euv;
         CodeRow cr;
-        load_partners<MODE>(wp, o_off, o_adj, o_d, len, shorter, u, Lu, sb, np, i0, dmax_chunk, v,
-                            ov, lv, duv, euv, cr);
+        load_partners<MODE, shorter>(wp, o_off, o_adj, o_d, len, u, Lu, sb, np, i0, dmax_chunk,
+                                     v, ov, lv, duv, euv, cr);
         for (uint64_t act = __ballot(lv > 0); act != 0; act &= act - 1, turn++) {
             if ((turn & (WPB - 1)) != wib) continue;
             const int si = (int)__builtin_ctzll(act);
@@ -672,12 +672,12 @@ __device__ void walk_flush(const WalkParams& wp, const double* __restrict__ o_d,
 
 // Both phases of the walk for one work-group: heavy items cooperatively, then light
 // items one per wave. Heaviest rows (highest ids) go first in both lists.
-template <int MODE>
+template <int MODE, bool shorter>
 __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_off,
                             const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                             const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
                             const int64_t* __restrict__ items, int64_t nl, int64_t nh,
-                            bool shorter, WalkShared& S, HistLds* H, WalkLaneState& st) {
+                            WalkShared& S, HistLds* H, WalkLaneState& st) {
     const int wib = threadIdx.x / UTRI_WAVE;
 #if UTRI_WALK_DYNAMIC
     // work queues: qctr[0] hands out heavy items to work-groups, qctr[1] light items to
@@ -690,8 +690,8 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         __syncthreads();
         if (q >= nh) break;
         const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, shorter,
-                              S.block, H, st);
+        walk_item_block<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq,
+                                       S.block, H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
 #ifndef UTRI_WALK_QGROUP
@@ -713,23 +713,23 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         const int64_t end = base + G < nl ? base + G : nl;
         for (int64_t q = base; q < end; q++) {
             const int64_t it = nl - 1 - q;
-            walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, shorter,
-                                 S.wave[wib], H, st);
+            walk_item_wave<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[it], it,
+                                          S.wave[wib], H, st);
         }
     }
 #else
     for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
         const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq, shorter,
-                              S.block, H, st);
+        walk_item_block<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq,
+                                       S.block, H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
     const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
     const int64_t W = (int64_t)gridDim.x * WPB;
     for (int64_t q = gw; q < nl; q += W) {
         const int64_t it = nl - 1 - q;
-        walk_item_wave<MODE>(wp, o_off, o_adj, o_d, len, perm, items[it], it, shorter,
-                             S.wave[wib], H, st);
+        walk_item_wave<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[it], it,
+                                      S.wave[wib], H, st);
     }
 #endif
 }
@@ -751,9 +751,13 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
         thresh_stage(wp.cvals, wp.nt);
     }
     WalkLaneState st;
-    walk_phases<MODE>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0], n_items_dev[1],
-                      stream_shorter<MODE>(n_items_dev), S,
-                      H, st);
+    // both partner sources as their own code (the choice is uniform over the launch)
+    if (stream_shorter<MODE>(n_items_dev))
+        walk_phases<MODE, true>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
+                                n_items_dev[1], S, H, st);
+    else
+        walk_phases<MODE, false>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
+                                 n_items_dev[1], S, H, st);
     walk_flush<MODE>(wp, o_d, H, st);
 }
 
@@ -784,9 +788,12 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
     else thresh_stage(sp.cvals, sp.nt);
     WalkLaneState st;
     if (wp.acc != nullptr) {
-        walk_phases<WALK_HIST>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                               n_items_dev[1], stream_shorter<WALK_HIST>(n_items_dev),
-                               S.walk, H, st);
+        if (stream_shorter<WALK_HIST>(n_items_dev))
+            walk_phases<WALK_HIST, true>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
+                                         n_items_dev[1], S.walk, H, st);
+        else
+            walk_phases<WALK_HIST, false>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
+                                          n_items_dev[1], S.walk, H, st);
         walk_flush<WALK_HIST>(wp, o_d, H, st);
     }
     __syncthreads();  // the walk's tables are no longer read; the sampler's reuse them
