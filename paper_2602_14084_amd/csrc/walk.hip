@@ -159,12 +159,20 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
         L = kept_prefix(off, dd, v, c);
         SL = kept_prefix(soff, sd, v, c);
     }
-    // one atomic per wave for each total
+    // one atomic per work-group for each total (atomics on one address serialise)
+    __shared__ uint64_t part[2][TPB / UTRI_WAVE];
     const uint64_t tl = utri_wave_sum_u64((uint64_t)L);
     const uint64_t tw = utri_wave_sum_u64((uint64_t)(SL - L) * (uint64_t)L);
     if (utri_lane() == 0) {
-        if (tl) atomicAdd(&kept[0], (unsigned long long)tl);
-        if (tw) atomicAdd(&kept[1], (unsigned long long)tw);
+        part[0][threadIdx.x / UTRI_WAVE] = tl;
+        part[1][threadIdx.x / UTRI_WAVE] = tw;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0;
+        for (int i = 0; i < TPB / UTRI_WAVE; i++) { a += part[0][i]; b += part[1][i]; }
+        if (a) atomicAdd(&kept[0], (unsigned long long)a);
+        if (b) atomicAdd(&kept[1], (unsigned long long)b);
     }
     if (v >= n) return;
     len[v] = L;
