@@ -236,6 +236,18 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
 int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream);
 
 /*
+ * Which row the triangle walk streams for each kept oriented edge u -> v (Section 4 visits
+ * the w in N+(u) ∩ N+(v); any of these orders visits every triangle once, so results do
+ * not depend on it). UTRI_ORDER_AUTO (the default) streams the shorter of the two kept
+ * rows when the plain forward iteration would stream at least 320 ids per kept edge on
+ * average, else N+(v); UTRI_ORDER_PLAIN always streams N+(v); UTRI_ORDER_SHORTER always
+ * streams the shorter row (the sign-world walk always streams N+(v)). Applies to later
+ * calls on g. Returns UTRI_E_INVALID for another value.
+ */
+enum { UTRI_ORDER_AUTO = 0, UTRI_ORDER_PLAIN = 1, UTRI_ORDER_SHORTER = 2 };
+int utri_set_walk_order(utri_graph* g, int order);
+
+/*
  * Work figures of one counting walk at t (the units the cost analysis of Theorem 5.1,
  * Section 5, sums over): out (host int64 [5]) =
  *   [0] m_c: oriented edges kept (sum of the kept oriented-row prefixes),

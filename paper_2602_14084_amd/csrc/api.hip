@@ -790,6 +790,13 @@ int utri_timing(utri_graph* g, int enable, double* ms, int64_t* launches) {
     return UTRI_OK;
 }
 
+int utri_set_walk_order(utri_graph* g, int order) {
+    UTRI_TRY(check_graph(g));
+    if (order < UTRI_ORDER_AUTO || order > UTRI_ORDER_SHORTER) return UTRI_E_INVALID;
+    g->walk_order = order;
+    return UTRI_OK;
+}
+
 int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream) {
     UTRI_TRY(check_graph(g));
     if (!t_ok(t)) return UTRI_E_INVALID;

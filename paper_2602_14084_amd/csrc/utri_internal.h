@@ -166,6 +166,7 @@ struct utri_graph {
     int sample_chunk = 128;         // draws per sampler group item
     int64_t sample_pass = UTRI_SAMPLE_PASS;  // draws grouped per sampler pass
     uint32_t sign_flush_at = 65535;          // sign-world counter additions between flushes
+    int walk_order = 0;                      // UTRI_ORDER_*: row streamed per kept edge
 
     // gradient: item counts of its four lists and partial-slice totals (they depend on the
     // degrees only), -1 = not read yet
@@ -398,6 +399,7 @@ struct WalkParams {
     const double* s_d = nullptr;
     const int32_t* s_eid = nullptr;
     const int32_t* slen = nullptr;
+    int order = 0;                      // UTRI_ORDER_* (set at launch)
 };
 
 // Negative-sign masks of `ww` words per edge (worlds 32 ww) for the sign-world walk.

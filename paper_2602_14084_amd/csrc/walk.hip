@@ -114,9 +114,10 @@ __host__ __device__ inline int partner_ranges(int32_t sl) { return sl > PR ? (sl
 #define UTRI_WALK_SHORTER_MIN 320
 #endif
 template <int MODE>
-__device__ inline bool stream_shorter(const int64_t* n_items_dev) {
-    return UTRI_WALK_SHORTER && MODE != WALK_SIGN &&
-           (double)n_items_dev[5] >= (double)UTRI_WALK_SHORTER_MIN * (double)n_items_dev[4];
+__device__ inline bool stream_shorter(const WalkParams& wp, const int64_t* n_items_dev) {
+    if (!UTRI_WALK_SHORTER || MODE == WALK_SIGN || wp.order == UTRI_ORDER_PLAIN) return false;
+    if (wp.order == UTRI_ORDER_SHORTER) return true;
+    return (double)n_items_dev[5] >= (double)UTRI_WALK_SHORTER_MIN * (double)n_items_dev[4];
 }
 
 // Bounds of the two item lists (a kept symmetric row of sl entries has at most
@@ -762,7 +763,7 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
     }
     WalkLaneState st;
     // both partner sources as their own code (the choice is uniform over the launch)
-    if (stream_shorter<MODE>(n_items_dev))
+    if (stream_shorter<MODE>(wp, n_items_dev))
         walk_phases<MODE, true>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
                                 n_items_dev[1], S, H, st);
     else
@@ -798,7 +799,7 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
     else thresh_stage(sp.cvals, sp.nt);
     WalkLaneState st;
     if (wp.acc != nullptr) {
-        if (stream_shorter<WALK_HIST>(n_items_dev))
+        if (stream_shorter<WALK_HIST>(wp, n_items_dev))
             walk_phases<WALK_HIST, true>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
                                          n_items_dev[1], S.walk, H, st);
         else
@@ -854,6 +855,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
 // and their kept prefixes (stored after the oriented ones), FP32 bounds of c.
 static void set_launch_fields(utri_graph* g, WalkParams& wp, const int32_t* len) {
     wp.lb = light_bound(g);
+    wp.order = g->walk_order;
     wp.s_off = g->s_off;
     wp.s_adj = g->s_adj;
     wp.s_d = g->s_d;

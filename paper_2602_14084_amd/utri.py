@@ -30,11 +30,12 @@ UTRI_PLAIN, UTRI_PRUNED, UTRI_PRUNED_L3 = 0, 1, 2
 UTRI_BAL, UTRI_UNBAL, UTRI_BOTH = 1, 2, 3
 UTRI_HOST_PTR, UTRI_DEVICE_PTR = 0, 1
 UTRI_SAMPLE_EDGE, UTRI_SAMPLE_VERTEX, UTRI_SAMPLE_EDGE_PLAIN, UTRI_SAMPLE_VERTEX_PLAIN = 0, 1, 2, 3
+UTRI_ORDER_AUTO, UTRI_ORDER_PLAIN, UTRI_ORDER_SHORTER = 0, 1, 2
 
 ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
-    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sign_worlds", "utri_sample", "utri_batch", "utri_autotune",
+    "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sign_worlds", "utri_sample", "utri_batch", "utri_autotune", "utri_set_walk_order",
     "utri_walk_stats", "utri_timing", "utri_strerror",
 ]
 
@@ -75,6 +76,7 @@ def lib():
     L.utri_sample.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, C.c_int, vp, vp]
     L.utri_batch.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, vp, vp, C.c_int, vp]
     L.utri_autotune.argtypes = [vp, f64, C.c_char_p, vp]
+    L.utri_set_walk_order.argtypes = [vp, C.c_int]
     L.utri_walk_stats.argtypes = [vp, f64, C.c_int, P(i64), vp]
     L.utri_timing.argtypes = [vp, C.c_int, P(f64), P(i64)]
     L.utri_strerror.argtypes = [C.c_int]
@@ -293,6 +295,10 @@ def utri_batch(h, ts, k, worlds, seed, use_graph=True, exact=None, est=None, wan
 def utri_autotune(h, t, cache_path=None, stream=None):
     cp = cache_path.encode() if cache_path else None
     _check(lib().utri_autotune(h, float(t), cp, _stream(stream)), "utri_autotune")
+
+
+def utri_set_walk_order(h, order):
+    _check(lib().utri_set_walk_order(h, int(order)), "utri_set_walk_order")
 
 
 def utri_walk_stats(h, t, method=UTRI_PRUNED, stream=None):

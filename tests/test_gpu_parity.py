@@ -59,6 +59,39 @@ def test_count_all_methods_match_oracle(dist):
         assert np.array_equal(got, want), (name, dist)
 
 
+@pytest.mark.parametrize("order", [utri.UTRI_ORDER_PLAIN, utri.UTRI_ORDER_SHORTER])
+def test_walk_orders_match_oracle(order):
+    """Both streamed-row orders of the walk (N+(v) always, or the shorter kept row of each
+    edge), forced on graphs where the automatic choice would take either one: counts,
+    threshold batches, enumeration, E, sign worlds and top-k against the oracle."""
+    for name, n, lo, hi in CASES + [("rmat16",) + inputs.rmat_graph(16, seed=7)]:
+        for dist in ["uniform", "bimodal"]:
+            p = inputs.draw_p(lo.shape[0], dist, 41)
+            og = oracle.load(n, lo, hi, p)
+            say("walk order", order, name, dist, "m", lo.shape[0])
+            g = gpu_graph(n, lo, hi, p)
+            utri.utri_set_walk_order(g.handle, order)
+            want = og.count_multi(TS)
+            for j, t in enumerate(TS):
+                for method in METHODS:
+                    assert g.count(t, method) == tuple(want[j]), (name, dist, t, method)
+            assert np.array_equal(g.count_batch(TS), want), (name, dist)
+            E0, _, _ = og.expected()
+            assert g.expected() == E0, (name, dist)
+            if lo.shape[0] < 20000:
+                ob, ou = og.enumerate(0.6)
+                bal, unb = g.enumerate(0.6)
+                assert np.array_equal(bal.cpu().numpy(), ob) and np.array_equal(unb.cpu().numpy(), ou)
+                assert np.array_equal(g.sign_worlds(64, 5).cpu().numpy(),
+                                      og.sign_worlds(64, 5)), (name, dist)
+                for which in (utri.UTRI_BAL, utri.UTRI_UNBAL):
+                    tri, sv = g.topk(100, which)
+                    wt, ws = og.topk(100, which)
+                    assert np.array_equal(tri.cpu().numpy(), wt) and np.array_equal(sv.cpu().numpy(), ws)
+    with pytest.raises(utri.UtriError):
+        utri.utri_set_walk_order(g.handle, 3)
+
+
 def test_count_which_selector():
     name, n, lo, hi = CASES[4]
     p = inputs.draw_p(lo.shape[0], "uniform", 1)
