@@ -113,11 +113,22 @@ __host__ __device__ inline int partner_ranges(int32_t sl) { return sl > PR ? (sl
 #ifndef UTRI_WALK_SHORTER_MIN
 #define UTRI_WALK_SHORTER_MIN 320
 #endif
+// The two totals are accumulated in KEPT_SLOTS slot pairs, 128 bytes apart, after the
+// four item counters (atomics on one address serialise).
+constexpr int KEPT_SLOTS = 64;
+constexpr int KEPT_STRIDE = 16;  // int64 per slot pair
+constexpr int NITEMS_WORDS = 4 + KEPT_SLOTS * KEPT_STRIDE;
+
 template <int MODE>
 __device__ inline bool stream_shorter(const WalkParams& wp, const int64_t* n_items_dev) {
     if (!UTRI_WALK_SHORTER || MODE == WALK_SIGN || wp.order == UTRI_ORDER_PLAIN) return false;
     if (wp.order == UTRI_ORDER_SHORTER) return true;
-    return (double)n_items_dev[5] >= (double)UTRI_WALK_SHORTER_MIN * (double)n_items_dev[4];
+    int64_t kept = 0, plain = 0;
+    for (int i = 0; i < KEPT_SLOTS; i++) {
+        kept += n_items_dev[4 + i * KEPT_STRIDE];
+        plain += n_items_dev[5 + i * KEPT_STRIDE];
+    }
+    return (double)plain >= (double)UTRI_WALK_SHORTER_MIN * (double)kept;
 }
 
 // Bounds of the two item lists (a kept symmetric row of sl entries has at most
@@ -131,9 +142,9 @@ inline int64_t heavy_bound(const utri_graph* g) {
 }
 
 // Kept prefixes at c of the oriented row (len) and of the symmetric row (slen) of each
-// vertex, and its light and heavy item counts. kept[0] += the kept oriented edges,
-// kept[1] += sum over v of (kept in-edges of v) * len(v): the ids the plain forward
-// iteration would stream.
+// vertex, and its light and heavy item counts. Over the slot pairs, kept[.][0] sums to the
+// kept oriented edges and kept[.][1] to the sum over v of (kept in-edges of v) * len(v):
+// the ids the plain forward iteration would stream.
 __device__ __forceinline__ int32_t kept_prefix(const int64_t* __restrict__ off,
                                                const double* __restrict__ dd, int64_t v, double c) {
     const int64_t a = off[v], b = off[v + 1];
@@ -160,7 +171,7 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
         L = kept_prefix(off, dd, v, c);
         SL = kept_prefix(soff, sd, v, c);
     }
-    // one atomic per work-group for each total (atomics on one address serialise)
+    // one atomic per work-group for each total, into one of KEPT_SLOTS slot pairs
     __shared__ uint64_t part[2][TPB / UTRI_WAVE];
     const uint64_t tl = utri_wave_sum_u64((uint64_t)L);
     const uint64_t tw = utri_wave_sum_u64((uint64_t)(SL - L) * (uint64_t)L);
@@ -172,8 +183,9 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
     if (threadIdx.x == 0) {
         uint64_t a = 0, b = 0;
         for (int i = 0; i < TPB / UTRI_WAVE; i++) { a += part[0][i]; b += part[1][i]; }
-        if (a) atomicAdd(&kept[0], (unsigned long long)a);
-        if (b) atomicAdd(&kept[1], (unsigned long long)b);
+        unsigned long long* k = kept + (blockIdx.x % KEPT_SLOTS) * KEPT_STRIDE;
+        if (a) atomicAdd(&k[0], (unsigned long long)a);
+        if (b) atomicAdd(&k[1], (unsigned long long)b);
     }
     if (v >= n) return;
     len[v] = L;
@@ -824,13 +836,13 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     UTRI_TRY(utri_scratch(g, SCR_ICNT, sizeof(int32_t) * (size_t)(2 * n + 2), &pcnt));
     UTRI_TRY(utri_scratch(g, SCR_IOFF, sizeof(int64_t) * (size_t)(2 * n + 2), &poff));
     UTRI_TRY(utri_scratch(g, SCR_ITEMS, sizeof(int64_t) * (size_t)(lb + hb), &pitems));
-    // [0] light items, [1] heavy items, [2..3] work-queue counters, [4] kept oriented
-    // edges, [5] ids the plain forward iteration would stream
-    UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * 6, &pn));
+    // [0] light items, [1] heavy items, [2..3] work-queue counters, then the slot pairs of
+    // the kept oriented edges and of the ids the plain forward iteration would stream
+    UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * NITEMS_WORDS, &pn));
     *items = (int64_t*)pitems;
     *n_items_dev = (int64_t*)pn;
     *len = (int32_t*)plen;
-    UTRI_TRY(utri_fill_u64(pn, 0, 6, s));
+    UTRI_TRY(utri_fill_u64(pn, 0, NITEMS_WORDS, s));
     if (n == 0) return UTRI_OK;
     int32_t* lcnt = (int32_t*)pcnt;
     int32_t* hcnt = lcnt + n;
@@ -840,7 +852,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     int32_t* slen = (int32_t*)plen + n + 1;
     hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, g->s_off,
                        g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt,
-                       (unsigned long long*)pn + 4);  // [4], [5]
+                       (unsigned long long*)pn + 4);
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
     UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
