@@ -102,7 +102,9 @@ __device__ inline int item_vertex(int64_t it) { return (int)(it & 0x7FFFFFFF); }
 __device__ inline int item_chunk(int64_t it) { return (int)(((uint64_t)it >> 32) & 0x7FF); }
 __device__ inline int item_range(int64_t it) { return (int)((uint64_t)it >> 43); }
 constexpr int64_t MAX_CHUNKS = 2048;
-__host__ __device__ inline int partner_ranges(int32_t sl) { return sl > PR ? (sl + PR - 1) / PR : 1; }
+__host__ __device__ inline int partner_ranges(int32_t sl) {
+    return sl > PR ? (int)(((int64_t)sl + PR - 1) / PR) : 1;
+}
 
 // Streaming the shorter row pays when the rows the plain forward iteration streams are
 // long: it then skips most of their strips, while scanning both ends' symmetric rows for
