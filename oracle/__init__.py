@@ -60,6 +60,12 @@ def _load():
     lib.orc_sign_negative.restype = C.c_int
     lib.orc_sign_worlds.argtypes = [vp, C.c_int32, C.c_uint64, _i64p]
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_threads.restype = C.c_int
+    lib.orc_probe_work.argtypes = [vp, _i64p, C.c_int64, _i64p]
+    lib.orc_hash_triples.argtypes = [_i32p, C.c_int64, C.c_int, _u64p, _i32p, C.c_int64, _i64p]
+    lib.orc_enumerate_digest.argtypes = [vp, C.c_double, C.c_int, _i64p, _u64p, _i32p,
+                                         C.c_int64, _i32p, C.c_int64, _i64p]
     _lib = lib
     return lib
 
@@ -76,6 +82,11 @@ class OracleError(RuntimeError):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_threads(n: int) -> int:
+    """Run later oracle calls on n OpenMP threads; returns the count in effect."""
+    return _load().orc_set_threads(int(n))
 
 
 class OracleGraph:
@@ -127,6 +138,15 @@ class OracleGraph:
             raise OracleError(rc, "count_vertices")
         return int(out[0]), int(out[1])
 
+    def probe_work(self, us):
+        """(probes of the node iterator over the vertices `us`, probes over all vertices)."""
+        us = np.ascontiguousarray(us, dtype=np.int64)
+        out = np.zeros(2, np.int64)
+        rc = self._lib.orc_probe_work(self._h, _p(us, _i64p), int(us.shape[0]), _p(out, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "probe_work")
+        return int(out[0]), int(out[1])
+
     def count_multi(self, ts):
         ts = np.ascontiguousarray(ts, dtype=np.float64)
         out = np.zeros((ts.shape[0], 2), np.int64)
@@ -148,6 +168,25 @@ class OracleGraph:
         if rc != OK:
             raise OracleError(rc, "enumerate")
         return bal[:counts[0]].copy(), unb[:counts[1]].copy()
+
+    def enumerate_digest(self, t, sample_bits=15, cap=1 << 20):
+        """The enumeration at t reduced to an order-free digest: (counts [2], digest [4] =
+        (sum, xor) of the balanced list then of the unbalanced one, sample_b, sample_u), the
+        samples being the triangles of each list whose hash has its top `sample_bits` bits
+        zero, sorted (see hash_triples)."""
+        counts = np.zeros(2, np.int64)
+        dig = np.zeros(4, np.uint64)
+        sb = np.zeros((cap, 3), np.int32)
+        su = np.zeros((cap, 3), np.int32)
+        ns = np.zeros(2, np.int64)
+        rc = self._lib.orc_enumerate_digest(self._h, float(t), int(sample_bits), _p(counts, _i64p),
+                                            _p(dig, _u64p), _p(sb, _i32p), int(cap), _p(su, _i32p),
+                                            int(cap), _p(ns, _i64p))
+        if rc != OK:
+            raise OracleError(rc, "enumerate_digest")
+        if ns[0] > cap or ns[1] > cap:
+            raise OracleError(E_CAPACITY, "enumerate_digest sample")
+        return counts, dig, sb[:ns[0]].copy(), su[:ns[1]].copy()
 
     def expected(self):
         """(E, T, S) with S the exact fixed-point sum of s as a Python int."""
@@ -264,6 +303,23 @@ class OracleGraph:
 
 def load(n, src, dst, p) -> OracleGraph:
     return OracleGraph(n, src, dst, p)
+
+
+def hash_triples(tri, sample_bits=15, cap=1 << 20):
+    """Order-free digest (sum mod 2^64, xor) of a list of triangles, int32 [k,3] with each
+    row sorted ascending, h(a, b, c) = splitmix64(splitmix64((a << 32) | b) + c), and the
+    spot sample: the rows whose h has its top `sample_bits` bits zero, in list order."""
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    out = np.zeros(2, np.uint64)
+    samp = np.zeros((cap, 3), np.int32)
+    ns = np.zeros(1, np.int64)
+    rc = _load().orc_hash_triples(_p(tri, _i32p), int(tri.shape[0]), int(sample_bits),
+                                  _p(out, _u64p), _p(samp, _i32p), int(cap), _p(ns, _i64p))
+    if rc != OK:
+        raise OracleError(rc, "hash_triples")
+    if ns[0] > cap:
+        raise OracleError(E_CAPACITY, "hash_triples sample")
+    return out, samp[:ns[0]].copy()
 
 
 def philox4x32_10(ctr, key):

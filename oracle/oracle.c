@@ -20,6 +20,10 @@
  *    node-iterator with hash sets: every pair of higher-ranked neighbours of a
  *    vertex is probed. Vertices are ranked by (degree, splitmix64(id)), a tie-break
  *    deliberately unlike the library's (degree, id) Node Order.
+ *  - orc_enumerate_digest / orc_hash_triples: the same enumeration reduced to an
+ *    order-free digest of each list (sum and xor of a hash of each sorted id triple)
+ *    plus a hash-selected spot sample, for graphs whose lists are too long to hold.
+ *    The lists are sets (Section 3), so an order-free digest is what can be compared.
  *  - The decision uses P_bal = (1 - s)/2 with s = d1*d2*d3 and d = 1 - 2*P+.
  *    This is the paper's four-term sum for P_bal (Section 3) in product form:
  *    P_bal >= t  <=>  s <= -(2t - 1),  P_unbal = 1 - P_bal > t  <=>  s > 2t - 1.
@@ -393,6 +397,37 @@ static int orc_threads(void) {
 
 int orc_num_threads(void) { return orc_threads(); }
 
+/* Use n OpenMP threads from now on (n >= 1); returns the count in effect. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#endif
+    return orc_threads();
+}
+
+/* Work of the node iterator, in hash probes: C(h, 2) for a vertex with h higher-ranked
+ * neighbours. out[0] = over the listed vertices, out[1] = over all vertices (so a timed
+ * run over the listed vertices scales to the whole graph by out[1] / out[0]). */
+int orc_probe_work(const orc_graph* g, const int64_t* us, int64_t k, int64_t out[2]) {
+    int64_t tot = 0, part = 0;
+    for (int64_t u = 0; u < g->n; u++) {
+        int64_t h = 0;
+        for (int64_t j = g->off[u]; j < g->off[u + 1]; j++)
+            if (g->rank[g->nbr[j]] > g->rank[u]) h++;
+        tot += h * (h - 1) / 2;
+    }
+    for (int64_t i = 0; i < k; i++) {
+        if (us[i] < 0 || us[i] >= g->n) return ORC_E_INVALID;
+        int64_t u = us[i], h = 0;
+        for (int64_t j = g->off[u]; j < g->off[u + 1]; j++)
+            if (g->rank[g->nbr[j]] > g->rank[u]) h++;
+        part += h * (h - 1) / 2;
+    }
+    out[0] = part;
+    out[1] = tot;
+    return ORC_OK;
+}
+
 typedef struct { int64_t v[8]; } orc_pad; /* one cache line of counters per thread */
 
 typedef struct {
@@ -545,6 +580,132 @@ int orc_enumerate(const orc_graph* g, double t, int32_t* bal, int64_t cap_b, int
     }
     for (int q = 0; q < th; q++) { free(cx.bal[q].buf); free(cx.unbal[q].buf); }
     free(cx.bal); free(cx.unbal); free(cx.fail);
+    return rc;
+}
+
+/* ---------------------------------------------------------------- enumeration digest */
+
+/* Order-free digest of a list of triangles, for lists too long to hold (the enumeration
+ * problem of Section 3 lists sets; their order is free). Each triangle is its id triple
+ * sorted ascending, a < b < c, hashed as
+ *     h(a, b, c) = splitmix64(splitmix64((a << 32) | b) + c)   (mod 2^64);
+ * a list's digest is (sum of h mod 2^64, xor of h). A spot sample keeps the triangles
+ * whose top `sample_bits` bits of h are zero, a deterministic subset that another
+ * implementation can pick out of its own list. */
+static uint64_t orc_triple_hash(int32_t a, int32_t b, int32_t c) {
+    uint64_t x = splitmix64(((uint64_t)(uint32_t)a << 32) | (uint64_t)(uint32_t)b);
+    return splitmix64(x + (uint64_t)(uint32_t)c);
+}
+
+static int orc_in_sample(uint64_t h, int sample_bits) {
+    if (sample_bits <= 0) return 1;
+    if (sample_bits >= 64) return h == 0;
+    return (h >> (64 - sample_bits)) == 0;
+}
+
+/* Digest (out[0] = sum, out[1] = xor) of n triples tri[n][3], each sorted ascending
+ * (ORC_E_INVALID otherwise), and the spot sample (up to cap triples copied to samp,
+ * *nsamp = how many qualify). */
+int orc_hash_triples(const int32_t* tri, int64_t n, int sample_bits, uint64_t out[2],
+                     int32_t* samp, int64_t cap, int64_t* nsamp) {
+    uint64_t s = 0, x = 0;
+    int64_t ns = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t a = tri[3 * i], b = tri[3 * i + 1], c = tri[3 * i + 2];
+        if (!(a < b && b < c)) return ORC_E_INVALID;
+        const uint64_t h = orc_triple_hash(a, b, c);
+        s += h;
+        x ^= h;
+        if (orc_in_sample(h, sample_bits)) {
+            if (ns < cap) { samp[3 * ns] = a; samp[3 * ns + 1] = b; samp[3 * ns + 2] = c; }
+            ns++;
+        }
+    }
+    out[0] = s;
+    out[1] = x;
+    *nsamp = ns;
+    return ORC_OK;
+}
+
+typedef struct {
+    const orc_graph* g;
+    double c;
+    uint64_t* acc;      /* [threads][8]: sum_b, xor_b, sum_u, xor_u, n_b, n_u (padded) */
+    orc_vec* samp_b;    /* [threads] */
+    orc_vec* samp_u;
+    int sample_bits;
+    int* fail;
+} digest_ctx;
+
+static void digest_visit(void* vctx, int tid, int32_t u, int32_t v, int32_t w, int32_t euv,
+                         int32_t euw, int32_t evw) {
+    digest_ctx* cx = (digest_ctx*)vctx;
+    const double* d = cx->g->d;
+    int k = orc_classify(orc_s(d[euv], d[euw], d[evw]), cx->c);
+    if (!k) return;
+    int32_t a = u, b = v, c = w, t;
+    if (b < a) { t = a; a = b; b = t; }
+    if (c < b) { t = b; b = c; c = t; }
+    if (b < a) { t = a; a = b; b = t; }
+    const uint64_t h = orc_triple_hash(a, b, c);
+    uint64_t* A = cx->acc + 8 * (size_t)tid + (k == 1 ? 0 : 2);
+    A[0] += h;
+    A[1] ^= h;
+    cx->acc[8 * (size_t)tid + 4 + (k - 1)]++;
+    if (orc_in_sample(h, cx->sample_bits)) {
+        orc_vec* dst = (k == 1) ? &cx->samp_b[tid] : &cx->samp_u[tid];
+        if (vec_push(dst, a, b, c)) cx->fail[tid] = 1;
+    }
+}
+
+/* The enumeration at t without storing it: counts[0..1] = list sizes, digest[0..1] =
+ * (sum, xor) of the balanced list and digest[2..3] of the unbalanced one (see
+ * orc_hash_triples), and each list's spot sample, sorted lexicographically, in
+ * samp_b / samp_u (up to cap_b / cap_u triples; ns[0..1] = how many qualify). */
+int orc_enumerate_digest(const orc_graph* g, double t, int sample_bits, int64_t counts[2],
+                         uint64_t digest[4], int32_t* samp_b, int64_t cap_b, int32_t* samp_u,
+                         int64_t cap_u, int64_t ns[2]) {
+    if (check_t(t)) return ORC_E_INVALID;
+    int th = orc_threads();
+    digest_ctx cx;
+    cx.g = g;
+    cx.c = orc_c(t);
+    cx.sample_bits = sample_bits;
+    cx.acc = (uint64_t*)calloc((size_t)th * 8, sizeof(uint64_t));
+    cx.samp_b = (orc_vec*)calloc((size_t)th, sizeof(orc_vec));
+    cx.samp_u = (orc_vec*)calloc((size_t)th, sizeof(orc_vec));
+    cx.fail = (int*)calloc((size_t)th, sizeof(int));
+    if (!cx.acc || !cx.samp_b || !cx.samp_u || !cx.fail) {
+        free(cx.acc); free(cx.samp_b); free(cx.samp_u); free(cx.fail);
+        return ORC_E_NOMEM;
+    }
+    int rc = orc_node_iterate(g, digest_visit, &cx, th);
+    for (int i = 0; i < 4; i++) digest[i] = 0;
+    counts[0] = counts[1] = 0;
+    ns[0] = ns[1] = 0;
+    for (int q = 0; q < th; q++) {
+        const uint64_t* A = cx.acc + 8 * (size_t)q;
+        digest[0] += A[0]; digest[1] ^= A[1];
+        digest[2] += A[2]; digest[3] ^= A[3];
+        counts[0] += (int64_t)A[4];
+        counts[1] += (int64_t)A[5];
+        if (cx.fail[q]) rc = ORC_E_NOMEM;
+        ns[0] += cx.samp_b[q].len;
+        ns[1] += cx.samp_u[q].len;
+    }
+    if (rc == ORC_OK) {
+        int64_t ib = 0, iu = 0;
+        for (int q = 0; q < th; q++) {
+            for (int64_t i = 0; i < cx.samp_b[q].len; i++, ib++)
+                if (ib < cap_b) memcpy(samp_b + 3 * ib, cx.samp_b[q].buf + 3 * i, 3 * sizeof(int32_t));
+            for (int64_t i = 0; i < cx.samp_u[q].len; i++, iu++)
+                if (iu < cap_u) memcpy(samp_u + 3 * iu, cx.samp_u[q].buf + 3 * i, 3 * sizeof(int32_t));
+        }
+        qsort(samp_b, (size_t)(ib < cap_b ? ib : cap_b), 3 * sizeof(int32_t), cmp_tri);
+        qsort(samp_u, (size_t)(iu < cap_u ? iu : cap_u), 3 * sizeof(int32_t), cmp_tri);
+    }
+    for (int q = 0; q < th; q++) { free(cx.samp_b[q].buf); free(cx.samp_u[q].buf); }
+    free(cx.acc); free(cx.samp_b); free(cx.samp_u); free(cx.fail);
     return rc;
 }
 

@@ -93,6 +93,105 @@ def test_counts_and_lists_match_bruteforce(dist):
             assert [tuple(r) for r in ou] == sorted(unb)
 
 
+@pytest.mark.parametrize("dist", ["dyadic16", "tri", "uniform", "half", "certain"])
+def test_count_multi_matches_bruteforce(dist):
+    """The multi-threshold count (one walk, every threshold classified per triangle) equals
+    the exact-rational brute force at each threshold, for thresholds in any order, repeated,
+    and 64 at once."""
+    rng = np.random.default_rng(5)
+    ladder = [0.5 + 0.0075 * j for j in range(64)]
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()):
+        p = inputs.draw_p(lo.shape[0], dist, 40 + gi)
+        g = load(n, lo, hi, p)
+        for ts in (TS, TS[::-1], list(rng.permutation(TS)) + [0.75, 0.5], ladder):
+            got = g.count_multi(ts)
+            assert got.shape == (len(ts), 2)
+            for j, t in enumerate(ts):
+                bal, unb = bf.classify_all(n, lo, hi, p, t)
+                assert tuple(got[j]) == (len(bal), len(unb)), (dist, gi, j, t)
+                assert tuple(got[j]) == g.count(t)
+
+
+def test_probe_work_counts_node_iterator_pairs():
+    """The node iterator's work (used to scale a timed vertex sample to the whole graph):
+    on the complete graph K_n the pair probes are C(n, 3); per-vertex work adds up, and
+    every triangle is one probe hit, so the total is at least T."""
+    from math import comb
+    for n in (5, 9, 12):
+        lo, hi = np.triu_indices(n, 1)
+        g = load(n, lo, hi, np.full(lo.shape[0], 0.3))
+        part, tot = g.probe_work(np.arange(n))
+        assert part == tot == comb(n, 3)
+    n, lo, hi = inputs.chung_lu_graph()
+    g = load(n, lo, hi, np.full(lo.shape[0], 0.5))
+    parts = [g.probe_work([v])[0] for v in range(n)]
+    assert sum(parts) == g.probe_work(np.arange(n))[1] >= sum(g.count(0.5))
+
+
+def _splitmix64(x):
+    M = (1 << 64) - 1
+    x = (x + 0x9E3779B97F4A7C15) & M
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & M
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & M
+    return x ^ (x >> 31)
+
+
+def _digest(tris, sample_bits):
+    """Sum mod 2^64 and xor of h(a,b,c) = splitmix64(splitmix64((a<<32)|b) + c), and the
+    triples whose h has its top sample_bits bits zero."""
+    M = (1 << 64) - 1
+    s = x = 0
+    samp = []
+    for a, b, c in tris:
+        h = _splitmix64((_splitmix64((a << 32) | b) + c) & M)
+        s = (s + h) & M
+        x ^= h
+        if h >> (64 - sample_bits) == 0:
+            samp.append((a, b, c))
+    return s, x, sorted(samp)
+
+
+@pytest.mark.parametrize("dist", ["dyadic16", "uniform", "certain"])
+def test_enumerate_digest_matches_bruteforce(dist):
+    """The order-free digest of the enumeration equals the digest of the exact-rational
+    brute-force lists (its hash written out independently here), with the same sizes and
+    spot samples."""
+    for gi, (n, lo, hi) in enumerate(tiny_graphs()):
+        p = inputs.draw_p(lo.shape[0], dist, 60 + gi)
+        g = load(n, lo, hi, p)
+        for t in TS:
+            bal, unb = bf.classify_all(n, lo, hi, p, t)
+            counts, dig, sb, su = g.enumerate_digest(t, sample_bits=1)
+            assert tuple(counts) == (len(bal), len(unb))
+            wb, wu = _digest(bal, 1), _digest(unb, 1)
+            assert (int(dig[0]), int(dig[1])) == wb[:2], (dist, gi, t)
+            assert (int(dig[2]), int(dig[3])) == wu[:2], (dist, gi, t)
+            assert [tuple(r) for r in sb] == wb[2]
+            assert [tuple(r) for r in su] == wu[2]
+
+
+def test_enumerate_digest_matches_lists_on_larger_graphs():
+    """On graphs past brute-force size the digest equals hash_triples over the full
+    enumerated lists, and a single changed triangle changes it."""
+    for n, lo, hi in [inputs.chung_lu_graph(), inputs.rmat_graph(11, seed=4)]:
+        p = inputs.draw_p(lo.shape[0], "uniform", 3)
+        g = load(n, lo, hi, p)
+        for t in (0.5, 0.6, 0.8):
+            bal, unb = g.enumerate(t)
+            counts, dig, sb, su = g.enumerate_digest(t, sample_bits=4)
+            assert tuple(counts) == (bal.shape[0], unb.shape[0])
+            hb, smp_b = oracle.hash_triples(bal, sample_bits=4)
+            hu, smp_u = oracle.hash_triples(unb, sample_bits=4)
+            assert list(dig) == list(hb) + list(hu)
+            assert np.array_equal(sb, smp_b) and np.array_equal(su, smp_u)  # lists are sorted
+            if bal.shape[0]:
+                other = bal.copy()
+                other[0, 2] += 1 if other[0, 2] + 1 not in other[0, :2] else 2
+                assert list(oracle.hash_triples(np.sort(other, axis=1))[0]) != list(hb)
+    with pytest.raises(oracle.OracleError):
+        oracle.hash_triples(np.array([[3, 2, 5]], np.int32))
+
+
 @pytest.mark.parametrize("dist", ["dyadic16", "uniform", "tri"])
 def test_expected_matches_exact_rational(dist):
     for gi, (n, lo, hi) in enumerate(tiny_graphs()):
