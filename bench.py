@@ -11,7 +11,10 @@ Printed on stdout: one JSON line (the contract fields plus `roofline`,
 `cpu_baseline` and `secondary`). Progress goes to stderr.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-secondary] [--no-cpu-baseline]
-                  [--only-main] [--copy-calibration]
+                  [--only-main] [--copy-calibration] [--cpu-full] [--cpu-detail]
+
+The counts are checked against the CPU oracle's whole-graph counts of the same workload
+(tests/golden/fullsize.json); the CPU baseline (the oracle) runs after all GPU timing.
 """
 from __future__ import annotations
 
@@ -20,7 +23,6 @@ import hashlib
 import json
 import os
 import sys
-import threading
 import time
 
 import numpy as np
@@ -82,6 +84,10 @@ def main():
     ap.add_argument("--only-main", action="store_true", help="main count timing only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle's whole count instead of a bounded sample")
+    ap.add_argument("--cpu-detail", action="store_true",
+                    help="also time the oracle on the small configurations, 1 and all threads")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -108,17 +114,6 @@ def main():
     log(f"generated R-MAT s{args.scale}: n={n} m={lo.shape[0]} in {time.time() - t0:.1f}s")
     workload = f"rmat_s{args.scale}_ef16_bimodal_pruned_count_t{args.tau}"
 
-    oracle_box = {}
-    oracle_thread = None
-    if not args.no_cpu_baseline:
-        def _oracle_load():
-            import oracle
-            t = time.time()
-            oracle_box["g"] = oracle.load(n, lo, hi, p)
-            oracle_box["load_s"] = time.time() - t
-        oracle_thread = threading.Thread(target=_oracle_load, daemon=True)
-        oracle_thread.start()
-
     src = torch.from_numpy(lo).to(dev)
     dst = torch.from_numpy(hi).to(dev)
     pp = torch.from_numpy(p).to(dev)
@@ -128,6 +123,7 @@ def main():
     torch.cuda.synchronize()
     load_ms = (time.perf_counter() - t) * 1e3
     del src, dst, pp
+    m_edges = g.m
     log(f"ingest {load_ms:.1f} ms, m={g.m}, max_deg={g.max_deg}")
 
     method = utri.UTRI_PRUNED
@@ -139,6 +135,12 @@ def main():
     walk_ms = walk_ms_total / max(1, launches)
     again = g.count(args.tau, method)
     assert again == counts, "counts differ between runs"
+    # the oracle's whole-graph counts (tests/golden/fullsize.json, written by the CPU
+    # oracle alone) for this exact workload: the benchmarked result must equal them
+    want = golden_counts(args.scale, args.tau)
+    if want is not None:
+        assert tuple(want) == tuple(counts), ("counts differ from the oracle's", counts, want)
+        log(f"counts equal the oracle's whole-graph counts {want}")
     teps = g.m / step_s
     stats = utri.utri_walk_stats(g.handle, args.tau, method)
     # staged-table algorithmic bytes: 4 B per streamed row id (each kept edge streams the
@@ -195,29 +197,17 @@ def main():
         torch.cuda.empty_cache()
         secondary.update(run_secondary(args, torch, inputs, utri, dev))
 
+    secondary["oracle_counts_equal"] = want is not None
+
     # ------------------------------------------------------------ CPU baseline (oracle)
+    # runs after every GPU measurement, so the host is idle while the GPU is timed
     cpu = None
-    if oracle_thread is not None:
-        oracle_thread.join()
-        og = oracle_box["g"]
-        import oracle
-        rng = np.random.default_rng(5)
-        k = max(1024, n // 512)
-        t = time.time()
-        og.count_vertices(args.tau, rng.choice(n, k, replace=False))
-        first = time.time() - t
-        k2 = int(min(n, max(k, k * 15.0 / max(first, 1e-3))))
-        us = rng.choice(n, k2, replace=False)
-        t = time.time()
-        og.count_vertices(args.tau, us)
-        t_sample = time.time() - t
-        t_full = t_sample * n / k2
-        cpu = {"value": og.m / t_full, "unit": "edges/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"node iterator over {k2} of {n} vertices drawn uniformly (seed 5) "
-                         f"at t={args.tau}, {t_sample:.1f}s, extrapolated by n/k; oracle load "
-                         f"{oracle_box['load_s']:.0f}s not timed"}
-        log(f"cpu baseline {cpu['value']:.3e} edges/s on {cpu['cores']} threads")
+    if not args.no_cpu_baseline:
+        del g
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(args, n, lo, hi, p, counts)
+        if args.cpu_detail:
+            secondary["cpu_detail"] = cpu_detail(inputs)
 
     traffic = measured_traffic(workload)
     line = {
@@ -233,7 +223,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "n": n, "m": g.m, "tau": args.tau, "method": "pruned",
+        "config": {"workload": workload, "n": n, "m": m_edges, "tau": args.tau, "method": "pruned",
                    "graph": f"R-MAT scale {args.scale}, edge factor 16, a=0.57 b=c=0.19, seed 1",
                    "p_dist": "0.5*Beta(0.5,8)+0.5*Beta(8,0.5), seed 2"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -244,6 +234,89 @@ def main():
         "secondary": secondary,
     }
     print(json.dumps(line), flush=True)
+
+
+def golden_counts(scale, tau):
+    """The CPU oracle's whole-graph counts of this workload, when they are on file."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)[f"rmat_s{scale}_bimodal"]
+        return rec["counts"].get(str(tau))
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(args, n, lo, hi, p, gpu_counts):
+    """The oracle (node iterator with hash sets, all host threads) on the same query.
+
+    Default: a bounded sample, vertices drawn uniformly (seed 5) until about 15 s of work,
+    scaled to the whole graph by the node iterator's pair probes (the sample's share of
+    them is computed exactly). --cpu-full times the whole count instead and checks it
+    against the GPU's."""
+    import oracle
+    t = time.time()
+    og = oracle.load(n, lo, hi, p)
+    load_s = time.time() - t
+    threads = oracle.num_threads()
+    log(f"oracle load {load_s:.1f}s on {threads} threads")
+    if args.cpu_full:
+        t = time.time()
+        full = og.count(args.tau)
+        t_full = time.time() - t
+        assert tuple(full) == tuple(gpu_counts), ("oracle and GPU counts differ", full, gpu_counts)
+        sample = (f"whole graph, node iterator at t={args.tau}: {t_full:.1f}s, counts equal "
+                  f"the GPU's; load {load_s:.0f}s not timed")
+    else:
+        rng = np.random.default_rng(5)
+        k = max(1024, n // 512)
+        t = time.time()
+        og.count_vertices(args.tau, rng.choice(n, k, replace=False))
+        first = time.time() - t
+        k2 = int(min(n, max(k, k * 15.0 / max(first, 1e-3))))
+        us = rng.choice(n, k2, replace=False)
+        t = time.time()
+        og.count_vertices(args.tau, us)
+        t_sample = time.time() - t
+        part, tot = og.probe_work(us)
+        t_full = t_sample * tot / max(part, 1)
+        sample = (f"node iterator at t={args.tau} over {k2} of {n} vertices drawn uniformly "
+                  f"(seed 5): {t_sample:.1f}s for {part / tot:.3f} of the whole graph's "
+                  f"{tot:.3e} pair probes, scaled by that share; load {load_s:.0f}s not timed")
+    log(f"cpu baseline {og.m / t_full:.3e} edges/s on {threads} threads")
+    return {"value": og.m / t_full, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": sample}
+
+
+def cpu_detail(inputs):
+    """Oracle timings on the small configurations, on one thread and on all of them: the
+    Chung-Lu count, enumeration and expected count; the R-MAT s20 counts."""
+    import oracle
+    out = {}
+    all_threads = oracle.num_threads()
+    n, lo, hi = inputs.chung_lu_graph()
+    p = inputs.draw_p(lo.shape[0], "uniform", 1)
+    og = oracle.load(n, lo, hi, p)
+    n2, lo2, hi2 = inputs.rmat_graph(20, seed=1)
+    p2 = inputs.draw_p(lo2.shape[0], "beta22", 2)
+    og2 = oracle.load(n2, lo2, hi2, p2)
+    for th in (1, all_threads):
+        oracle.set_threads(th)
+        r = {}
+        for name, fn in (("count_t0.6", lambda: og.count(0.6)),
+                         ("enumerate_t0.6", lambda: og.enumerate(0.6)),
+                         ("expected", lambda: og.expected())):
+            t = time.time()
+            fn()
+            r["chung_lu_" + name + "_ms"] = (time.time() - t) * 1e3
+        for tau in (0.5, 0.7, 0.9):
+            t = time.time()
+            og2.count(tau)
+            r[f"rmat_s20_beta22_count_t{tau}_s"] = time.time() - t
+        out[f"threads_{th}"] = r
+        log(f"cpu detail on {th} threads: {r}")
+    oracle.set_threads(all_threads)
+    return out
 
 
 def run_secondary(args, torch, inputs, utri, dev):

@@ -299,7 +299,8 @@ int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int
 
 int utri_graph_free(utri_graph* g) {
     if (!g) return UTRI_OK;
-    (void)hipDeviceSynchronize();
+    // the handle's own replay stream first; hipFree then waits for the device itself
+    if (g->batch.stream) (void)hipStreamSynchronize(g->batch.stream);
     utri_free_graph_internal(g);
     return UTRI_OK;
 }
@@ -705,8 +706,13 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
     UTRI_HIP_TRY(hipEventRecord(B.ev, s));
     UTRI_HIP_TRY(hipStreamWaitEvent(B.stream, B.ev, 0));
     hipStream_t gs = B.stream;
+    // a captured graph is reused only with the same shape, outputs, scratch buffers (no
+    // reallocation since capture) and launch shape (the autotuner may have changed it)
     const bool same = B.exec && B.nt == nt && B.k == k && B.worlds == worlds && B.exact == exact &&
-                      B.est == est && B.cvals == cv;
+                      B.est == est && B.cvals == cv && B.scr_gen == g->scr_gen &&
+                      B.walk_blocks_per_cu == g->walk_blocks_per_cu &&
+                      B.sample_chunk == g->sample_chunk && B.sample_pass == g->sample_pass &&
+                      B.walk_order == g->walk_order;
     if (!same) {
         if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
         if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
@@ -730,6 +736,11 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
         B.exact = exact;
         B.est = est;
         B.cvals = cv;
+        B.scr_gen = g->scr_gen;
+        B.walk_blocks_per_cu = g->walk_blocks_per_cu;
+        B.sample_chunk = g->sample_chunk;
+        B.sample_pass = g->sample_pass;
+        B.walk_order = g->walk_order;
     }
     // thresholds and seed are read from device buffers written above on `s`
     UTRI_HIP_TRY(hipGraphLaunch(B.exec, gs));
@@ -801,9 +812,17 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
     UTRI_TRY(check_graph(g));
     if (!t_ok(t)) return UTRI_E_INVALID;
     hipStream_t s = as_stream(hip_stream);
-    hipEvent_t e0, e1;
-    UTRI_HIP_TRY(hipEventCreate(&e0));
-    UTRI_HIP_TRY(hipEventCreate(&e1));
+    // events are released on every return path
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    UTRI_HIP_TRY(hipEventCreate(&ev.a));
+    UTRI_HIP_TRY(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     int64_t out[2];
     float best = 1e30f;
     int best_b = g->walk_blocks_per_cu;
@@ -826,23 +845,24 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
     g->walk_blocks_per_cu = best_b;
     // draws per sampler group item
     std::vector<double> tv{t};
-    double* est = nullptr;
     const int32_t worlds = 64;
     const int64_t k = 4096;
-    UTRI_HIP_TRY(hipMalloc(&est, sizeof(double) * worlds * 2));
+    void* pest;
+    UTRI_TRY(utri_scratch(g, SCR_TUNE, sizeof(double) * worlds * 2, &pest));
+    double* est = (double*)pest;
     float best_s = 1e30f;
     int best_c = g->sample_chunk;
     for (int c : {64, 128, 256, 512}) {
         g->sample_chunk = c;
         int rc = utri_sample(g, tv.data(), 1, k, worlds, 12345, UTRI_SAMPLE_EDGE, est, hip_stream);
-        if (rc != UTRI_OK) { (void)hipFree(est); return rc; }
+        if (rc != UTRI_OK) return rc;
         float tot = 0.f;
         for (int r = 0; r < 3; r++) {
             UTRI_HIP_TRY(hipEventRecord(e0, s));
             rc = utri_sample(g, tv.data(), 1, k, worlds, 12345, UTRI_SAMPLE_EDGE, est, hip_stream);
             UTRI_HIP_TRY(hipEventRecord(e1, s));
             UTRI_HIP_TRY(hipEventSynchronize(e1));
-            if (rc != UTRI_OK) { (void)hipFree(est); return rc; }
+            if (rc != UTRI_OK) return rc;
             float ms = 0.f;
             UTRI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             tot += ms;
@@ -850,9 +870,6 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
         if (tot < best_s) { best_s = tot; best_c = c; }
     }
     g->sample_chunk = best_c;
-    (void)hipFree(est);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {

@@ -337,6 +337,7 @@ int utri_scratch(utri_graph* g, int slot, size_t bytes, void** out) {
         if (g->scr[slot]) UTRI_HIP_TRY(hipFree(g->scr[slot]));
         g->scr[slot] = nullptr;
         g->scr_bytes[slot] = 0;
+        g->scr_gen++;  // any captured batch graph holding the old address is stale now
         size_t want = bytes + bytes / 8;
         hipError_t e = hipMalloc(&g->scr[slot], want);
         if (e != hipSuccess) {
@@ -421,6 +422,9 @@ int utri_build_rows(utri_graph* g, hipStream_t s) {
     g->idmask = (nbits >= 32) ? 0xFFFFFFFFu : ((1u << nbits) - 1u);
     const int spare = 32 - (int)nbits;
     g->code_mb = (spare >= 3) ? std::min(spare - 1, 15) : 0;
+    // UTRI_CODE_MB caps the magnitude bits (0 = no code): narrow codes on small graphs take
+    // the decision path that large graphs take; results never depend on the width
+    if (const char* e = getenv("UTRI_CODE_MB")) g->code_mb = std::max(0, std::min(g->code_mb, atoi(e)));
     if (g->code_mb > 0) {
         hipLaunchKernelGGL(k_pack_oriented, dim3(blocks_for(m)), dim3(TPB), 0, s, g->o_adj, g->o_d,
                            m, g->idbits, g->code_mb);

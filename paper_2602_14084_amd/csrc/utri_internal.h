@@ -105,6 +105,7 @@ enum UtriScratch {
     SCR_TOPK_IDX,     // u32 [2N] sort values
     SCR_SIGN_MASK,    // u32 [m][worlds / 32] negative-sign masks of the sign worlds
     SCR_SIGN_CNT,     // u64 [worlds] balanced triangles per sign world
+    SCR_TUNE,         // f64 estimates written by the autotuner's sampler trials
     SCR_COUNT
 };
 
@@ -119,6 +120,11 @@ struct UtriBatchGraph {
     int32_t worlds = 0;
     int64_t* exact = nullptr;
     double* est = nullptr;
+    // the graph holds raw pointers to the handle's scratch buffers and bakes in its launch
+    // shape: it is replayed only while neither has changed since capture
+    uint64_t scr_gen = 0;
+    int walk_blocks_per_cu = 0, sample_chunk = 0, walk_order = 0;
+    int64_t sample_pass = 0;
 };
 
 struct utri_graph {
@@ -159,6 +165,7 @@ struct utri_graph {
 
     void* scr[SCR_COUNT] = {};
     size_t scr_bytes[SCR_COUNT] = {};
+    uint64_t scr_gen = 0;  // bumped whenever a scratch buffer is reallocated
 
     // launch shape (set by the autotuner, else defaults)
     int walk_blocks_per_cu = 0;     // 0: the kernel's resident occupancy

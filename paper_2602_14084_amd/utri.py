@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -332,7 +333,11 @@ class Graph:
         self.n, self.m = info["n"], info["m"]
         self.self_loops, self.dups, self.max_deg = (info["self_loops_dropped"],
                                                     info["dups_merged"], info["max_deg"])
-        self._p_version = None
+        # P+ bookkeeping for expected_balanced: a counter bumped by every set_p, and the
+        # tensor (weakly referenced, with its version) the current P+ was last set from
+        self._p_token = 0
+        self._p_src = None
+        self._p_src_version = None
 
     @property
     def handle(self):
@@ -354,6 +359,17 @@ class Graph:
 
     def set_p(self, p):
         utri_graph_set_p(self._h, p)
+        self._p_token += 1
+        self._p_src = None
+        self._p_src_version = None
+
+    def _set_p_from(self, p):
+        """Make p (a tensor) the graph's P+ unless it already is, unchanged since."""
+        src = self._p_src() if self._p_src is not None else None
+        if src is not p or self._p_src_version != p._version:
+            self.set_p(p.detach())
+            self._p_src = weakref.ref(p)
+            self._p_src_version = p._version
 
     def count(self, t, method=UTRI_PRUNED, which=UTRI_BOTH):
         return utri_count(self._h, t, method, which)
@@ -399,24 +415,30 @@ def _make_expected_balanced():
         """E(p) = expected number of balanced triangles; backward gives dE/dp per edge.
 
         forward(p, graph): p is a float64 tensor [m] of P+ in the graph's edge-id order.
-        The graph's P+ is replaced by p (rows re-sorted) unless p is the tensor it was
-        last set from, then E is computed by the walk. backward multiplies the
-        edge-centric gradient kernel's output by the incoming gradient.
+        The graph's P+ is replaced by p (rows re-sorted) unless it was last set from this
+        same tensor object, unmodified since; then E is computed by the walk. backward
+        re-sets the graph's P+ to the forward's p if anything changed it in between
+        (another forward, a direct set_p), then multiplies the edge-centric gradient
+        kernel's output by the incoming gradient.
         """
 
         @staticmethod
         def forward(ctx, p, graph):
-            key = (p.data_ptr(), p._version)
-            if graph._p_version != key:
-                graph.set_p(p.detach())
-                graph._p_version = key
+            graph._set_p_from(p)
             ctx.graph = graph
+            ctx.token = graph._p_token
+            ctx.save_for_backward(p)  # autograd rejects backward if p is modified in place
             E = graph.expected()
             return torch.tensor(E, dtype=torch.float64, device=p.device)
 
         @staticmethod
         def backward(ctx, gout):
-            g = ctx.graph.expected_grad()
+            (p,) = ctx.saved_tensors
+            graph = ctx.graph
+            if graph._p_token != ctx.token:
+                graph._set_p_from(p)
+                ctx.token = graph._p_token
+            g = graph.expected_grad()
             return gout.to(g.device) * g, None
 
     return ExpectedBalanced

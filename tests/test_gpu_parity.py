@@ -560,3 +560,146 @@ def test_error_paths():
     # the handle stays usable after errors; an empty graph works too
     e = gpu_graph(5, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0))
     assert e.m == 0 and e.count(0.6) == (0, 0) and e.expected() == 0.0
+
+
+@pytest.mark.parametrize("mb", [1, 3, 8])
+def test_narrow_codes_match_oracle(monkeypatch, mb):
+    """The d codes packed above the ids decide most triangles; capped at mb magnitude bits
+    (the s23 benchmark graph has 8) the undecided band widens and the exact rule takes over
+    more often, and every result stays the oracle's, exact dyadic ties included."""
+    monkeypatch.setenv("UTRI_CODE_MB", str(mb))
+    ts = TS
+    for name, n, lo, hi in [CASES[4], CASES[5], CASES[6]]:
+        for dist in ("dyadic16", "tri", "uniform", "bimodal"):
+            p = inputs.draw_p(lo.shape[0], dist, 77)
+            og = oracle.load(n, lo, hi, p)
+            want = og.count_multi(ts)
+            say("codes", mb, name, dist)
+            g = gpu_graph(n, lo, hi, p)
+            for order in (utri.UTRI_ORDER_PLAIN, utri.UTRI_ORDER_SHORTER):
+                utri.utri_set_walk_order(g.handle, order)
+                for j, t in enumerate(ts):
+                    for method in METHODS:
+                        assert g.count(t, method) == tuple(want[j]), (mb, name, dist, order, t, method)
+                assert np.array_equal(g.count_batch(ts), want)
+            for t in (0.5625, 0.75, 0.9375):
+                ob, ou = og.enumerate(t)
+                b, u = g.enumerate(t)
+                assert np.array_equal(b.cpu().numpy(), ob) and np.array_equal(u.cpu().numpy(), ou)
+            ex, es = g.batch(ts, 300, 4, 5, use_graph=False)
+            assert np.array_equal(ex.cpu().numpy(), want)
+            assert np.array_equal(es.cpu().numpy(), og.sample(ts, 300, 4, 5)[0])
+
+
+def test_batch_graph_survives_scratch_growth():
+    """A captured batch graph holds the handle's scratch addresses: calls that grow those
+    buffers in between (a sorted enumeration, a sampler run with more worlds, a count after
+    an estimate-only batch, a new launch shape) must not leave a replay writing into freed
+    memory; every replay still equals the oracle."""
+    n, lo, hi = inputs.rmat_graph(13, seed=9)
+    p = inputs.draw_p(lo.shape[0], "beta22", 2)
+    og = oracle.load(n, lo, hi, p)
+    ts = [0.5 + 0.0075 * j for j in range(64)]
+    k, W, seed = 600, 16, 77
+    want_exact = og.count_multi(ts)
+    want_est, _ = og.sample(ts, k, W, seed)
+    g = gpu_graph(n, lo, hi, p)
+    side = torch.cuda.Stream()
+
+    def replay(exact_too=True):
+        ex = torch.full((64, 2), -1, dtype=torch.int64, device="cuda") if exact_too else None
+        es = torch.full((W, 64, 2), -1.0, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(side):
+            g.batch(ts, k, W, seed, use_graph=True, exact=ex, est=es, want_exact=exact_too)
+        torch.cuda.synchronize()
+        if exact_too:
+            assert np.array_equal(ex.cpu().numpy(), want_exact)
+        assert np.array_equal(es.cpu().numpy(), want_est)
+
+    say("graph batch before growth")
+    replay()
+    replay()
+    b, u = g.enumerate(0.5, sorted=True)  # grows the sort and rocPRIM buffers
+    ob, ou = og.enumerate(0.5)
+    assert np.array_equal(b.cpu().numpy(), ob) and np.array_equal(u.cpu().numpy(), ou)
+    say("graph batch after a sorted enumeration")
+    replay()
+    big = g.sample(ts, 50, 300, 3).cpu().numpy()  # grows the per-world histograms
+    assert np.array_equal(big, og.sample(ts, 50, 300, 3)[0])
+    say("graph batch after a 300-world sample")
+    replay()
+    replay(exact_too=False)  # estimate-only capture: small item counters
+    assert g.count(0.7) == og.count(0.7)  # a walk regrows them
+    say("graph batch (estimates only) after a count")
+    replay(exact_too=False)
+    g.autotune(0.7)  # may change the launch shape
+    say("graph batch after autotune")
+    replay()
+
+
+def test_expected_balanced_follows_each_forward():
+    """Two forwards with different P+, then the first one's backward: its gradient is taken
+    at its own P+; a direct set_p between forward and backward does not leak into it; a new
+    tensor with the same values gives the same E."""
+    n, lo, hi = inputs.chung_lu_graph(500, 2.5, 4000.0, 12)
+    m = lo.shape[0]
+    p1 = inputs.draw_p(m, "uniform", 1)
+    p2 = inputs.draw_p(m, "uniform_05_95", 2)
+    p3 = inputs.draw_p(m, "beta22", 3)
+    o1, o2 = oracle.load(n, lo, hi, p1), oracle.load(n, lo, hi, p2)
+    g = gpu_graph(n, lo, hi, p3)
+    t1 = torch.from_numpy(p1).cuda().requires_grad_(True)
+    t2 = torch.from_numpy(p2).cuda().requires_grad_(True)
+    say("autograd two forwards")
+    E1 = utri.expected_balanced(t1, g)
+    E2 = utri.expected_balanced(t2, g)
+    assert E1.item() == o1.expected()[0] and E2.item() == o2.expected()[0]
+    E1.backward()
+    assert np.array_equal(t1.grad.cpu().numpy(), o1.grad())
+    g.set_p(p3)
+    E2.backward()
+    assert np.array_equal(t2.grad.cpu().numpy(), o2.grad())
+    # set_p from numpy, then the same tensor object again: E is recomputed at t1's values
+    g.set_p(p2)
+    assert utri.expected_balanced(t1, g).item() == o1.expected()[0]
+    t1b = torch.from_numpy(p1.copy()).cuda()
+    assert utri.expected_balanced(t1b, g).item() == o1.expected()[0]
+    # an in-place change of the same tensor is seen
+    with torch.no_grad():
+        t1b.copy_(torch.from_numpy(p2))
+    assert utri.expected_balanced(t1b, g).item() == o2.expected()[0]
+
+
+def test_sweeps_match_oracle(tmp_path):
+    """Every count of the experiment sweeps equals the oracle's, and every MAPE value equals
+    the one computed from the oracle alone (its replay of the same estimator runs against
+    its exact counts)."""
+    from paper_2602_14084_amd import sweeps
+    out = tmp_path / "sw.json"
+    say("sweeps quick vs oracle")
+    sweeps.main(["--quick", "--out", str(out)])
+    import json
+    res = json.loads(out.read_text())
+    n, lo, hi = inputs.rmat_graph(12, seed=1)
+    og = oracle.load(n, lo, hi, inputs.draw_p(lo.shape[0], "beta22", 2))
+    want = og.count_multi(sweeps.TS)
+    for j, row in enumerate(res["exact_rmat_s12_beta22"]):
+        assert tuple(row["counts"]) == tuple(want[j]), row["t"]
+    for dist, rows in res["distributions_rmat_s12"].items():
+        od = oracle.load(n, lo, hi, inputs.draw_p(lo.shape[0], dist, 2)).count_multi(sweeps.TS)
+        for j, row in enumerate(rows):
+            assert tuple(row["counts"]) == tuple(od[j]), (dist, row["t"])
+    nb, lob, hib = inputs.rmat_graph(13, seed=1)
+    ob = oracle.load(nb, lob, hib, inputs.draw_p(lob.shape[0], "bimodal", 2)).count_multi(sweeps.TS)
+    for j, row in enumerate(res["exact_rmat_s13_bimodal"]):
+        assert tuple(row["counts"]) == tuple(ob[j]), row["t"]
+    m = res["mape_rmat_s12_beta22"]
+    exact = np.array(og.count(m["t"]), np.float64)
+    assert m["exact"] == exact.tolist()
+    for name, fn in (("edge", og.sample), ("vertex", og.sample_vertices)):
+        for row in m[name]:
+            est = fn([m["t"]], row["k"], m["runs"], 2026)[0][:, 0, :]
+            for c, key in enumerate(("mape_balanced", "mape_unbalanced")):
+                if exact[c] > 0:
+                    want_mape = float(np.mean(np.abs(est[:, c] - exact[c]) / exact[c]))
+                    assert row[key] == want_mape, (name, row["k"], key)
