@@ -82,7 +82,8 @@ enum { UTRI_SAMPLE_EDGE = 0, UTRI_SAMPLE_VERTEX = 1, UTRI_SAMPLE_EDGE_PLAIN = 2,
  * Value" / "Absolute Edge Order", Section 5), per-row hash tables, and the degree
  * orientation of Definition "Node Order" (Section 4) with vertices relabelled by it.
  * Errors: UTRI_E_INVALID (NULL with m_in > 0, id out of range, bad P+),
- * UTRI_E_CONFLICT, UTRI_E_RANGE (n >= 2^31 or m >= 2^31), UTRI_E_NOMEM, UTRI_E_HIP.
+ * UTRI_E_CONFLICT, UTRI_E_RANGE (n >= 2^31, m_in >= 2^31 or m >= 2^31), UTRI_E_NOMEM,
+ * UTRI_E_HIP.
  * On error *out is NULL.
  */
 int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int64_t m_in,
@@ -126,6 +127,8 @@ int utri_count_batch(utri_graph* g, const double* t, int nt, int method, int64_t
  * it in a deterministic walk order. A class not selected by `which` is neither
  * written nor counted. If a list exceeds its capacity nothing is written for it and
  * UTRI_E_CAPACITY is returned with the sizes filled in, so the caller can retry.
+ * Sorting a list of 2^32 triangles or more returns UTRI_E_RANGE (the unsorted list is
+ * written).
  * Waits for the stream.
  */
 int utri_enumerate(utri_graph* g, double t, int method, int which, int32_t* bal, int64_t cap_b,

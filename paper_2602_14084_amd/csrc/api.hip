@@ -57,40 +57,37 @@ int check_graph(const utri_graph* g) { return g ? UTRI_OK : UTRI_E_INVALID; }
 __global__ void k_tri_keys(const int32_t* __restrict__ tri, int64_t cnt, unsigned nb,
                            uint64_t* __restrict__ k_lo, uint32_t* __restrict__ k_hi,
                            uint32_t* __restrict__ idx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    k_lo[i] = ((uint64_t)(uint32_t)tri[3 * i + 1] << nb) | (uint64_t)(uint32_t)tri[3 * i + 2];
-    k_hi[i] = (uint32_t)tri[3 * i];
-    idx[i] = (uint32_t)i;
+    UTRI_FOR_GRID(i, cnt) {
+        k_lo[i] = ((uint64_t)(uint32_t)tri[3 * i + 1] << nb) | (uint64_t)(uint32_t)tri[3 * i + 2];
+        k_hi[i] = (uint32_t)tri[3 * i];
+        idx[i] = (uint32_t)i;
+    }
 }
 
 __global__ void k_tri_key_first(const int32_t* __restrict__ tri, const uint32_t* __restrict__ idx,
                                 int64_t cnt, uint32_t* __restrict__ k) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) k[i] = (uint32_t)tri[3 * (int64_t)idx[i]];
+    UTRI_FOR_GRID(i, cnt) k[i] = (uint32_t)tri[3 * (int64_t)idx[i]];
 }
 
 __global__ void k_tri_gather(const int32_t* __restrict__ tri, const uint32_t* __restrict__ idx,
                              int64_t cnt, int32_t* __restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int64_t j = idx[i];
-    out[3 * i] = tri[3 * j];
-    out[3 * i + 1] = tri[3 * j + 1];
-    out[3 * i + 2] = tri[3 * j + 2];
+    UTRI_FOR_GRID(i, cnt) {
+        const int64_t j = idx[i];
+        out[3 * i] = tri[3 * j];
+        out[3 * i + 1] = tri[3 * j + 1];
+        out[3 * i + 2] = tri[3 * j + 2];
+    }
 }
 
 __global__ void k_copy_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
+    UTRI_FOR_GRID(i, n) b[i] = a[i];
 }
 
-inline int nblk(int64_t n) { return (int)((n + 255) / 256); }
+inline unsigned nblk(int64_t n) { return utri_grid(n, 256); }
 
 __global__ void k_check_eids(const int64_t* __restrict__ eids, int64_t k, int64_t m,
                              uint32_t* __restrict__ flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k && (eids[i] < 0 || eids[i] >= m)) atomicOr(flag, 1u);
+    UTRI_FOR_GRID(i, k) if (eids[i] < 0 || eids[i] >= m) atomicOr(flag, 1u);
 }
 
 template <class K, class V>
@@ -109,6 +106,7 @@ int radix_pairs(utri_graph* g, const K* kin, K* kout, const V* vin, V* vout, int
 // Lexicographic sort of cnt int32 triples in place (two stable LSD radix passes).
 int sort_triples(utri_graph* g, int32_t* tri, int64_t cnt, hipStream_t s) {
     if (cnt <= 1) return UTRI_OK;
+    if (cnt > (int64_t)UINT32_MAX) return UTRI_E_RANGE;  // positions are 32-bit sort values
     unsigned nb = 1;
     while (((int64_t)1 << nb) < g->n) nb++;
     void *pa, *pb, *pc, *pd;
@@ -284,6 +282,9 @@ int utri_graph_load(const int64_t* src, const int64_t* dst, const double* p, int
     if (ptr_kind != UTRI_HOST_PTR && ptr_kind != UTRI_DEVICE_PTR) return UTRI_E_INVALID;
     if (m_in > 0 && (!src || !dst || !p)) return UTRI_E_INVALID;
     if (n >= ((int64_t)1 << 31)) return UTRI_E_RANGE;
+    // the canonical graph has fewer than 2^31 edges, so more input edges than that could
+    // only be duplicates; the load's per-input-edge kernels assume it
+    if (m_in >= ((int64_t)1 << 31)) return UTRI_E_RANGE;
     utri_graph* g = nullptr;
     int rc = utri_load_internal(src, dst, p, m_in, n, ptr_kind, as_stream(hip_stream), &g);
     if (rc != UTRI_OK) return rc;

@@ -276,8 +276,7 @@ __global__ void k_hinsert(const int32_t* __restrict__ s_row, const int32_t* __re
 }
 
 __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t v, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    UTRI_FOR_GRID(i, n) p[i] = v;
 }
 
 __global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
@@ -352,7 +351,7 @@ int utri_scratch(utri_graph* g, int slot, size_t bytes, void** out) {
 
 int utri_fill_u64(void* p, uint64_t v, int64_t count, hipStream_t s) {
     if (count <= 0) return UTRI_OK;
-    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(count)), dim3(TPB), 0, s, (uint64_t*)p, v, count);
+    hipLaunchKernelGGL(k_fill_u64, dim3(utri_grid(count, TPB)), dim3(TPB), 0, s, (uint64_t*)p, v, count);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }

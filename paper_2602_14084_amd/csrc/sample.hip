@@ -191,13 +191,13 @@ __global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double*
 __global__ void k_v_draw(uint64_t seed, int64_t k, int64_t T, int64_t n,
                          const int32_t* __restrict__ inv, const int32_t* __restrict__ slen,
                          int32_t* __restrict__ vq, int32_t* __restrict__ vlen) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    const int32_t world = (int32_t)(t / k);
-    const int64_t i = t - (int64_t)world * k;
-    const int32_t q = inv[utri_sample_vertex(seed, (uint32_t)world, (uint64_t)i, n)];
-    vq[t] = q;
-    vlen[t] = slen[q];
+    UTRI_FOR_GRID(t, T) {
+        const int32_t world = (int32_t)(t / k);
+        const int64_t i = t - (int64_t)world * k;
+        const int32_t q = inv[utri_sample_vertex(seed, (uint32_t)world, (uint64_t)i, n)];
+        vq[t] = q;
+        vlen[t] = slen[q];
+    }
 }
 
 // One wave per vertex draw writes the edge records of the vertex's prefix.
@@ -443,7 +443,7 @@ int utri_vertex_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, hi
     int32_t* vq = (int32_t*)pq;
     int32_t* vlen = (int32_t*)pl;
     int64_t* voff = (int64_t*)po;
-    hipLaunchKernelGGL(k_v_draw, dim3(blocks_for(T)), dim3(TPB), 0, s, sp.seed, sp.k, T, g->n,
+    hipLaunchKernelGGL(k_v_draw, dim3(utri_grid(T, TPB)), dim3(TPB), 0, s, sp.seed, sp.k, T, g->n,
                        (const int32_t*)g->inv, slen, vq, vlen);
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, vlen, voff, T, voff + T, s));

@@ -33,6 +33,19 @@
 // most sampler draws grouped per pass (records of 8 bytes each)
 #define UTRI_SAMPLE_PASS (1ll << 27)
 
+// A dispatch's work-item count (blocks x threads) must stay below 2^32: one-dimensional
+// launches over arrays that can be longer than that (enumerated triangles, sign masks,
+// caller-sized draws) cap their grid here and their kernels stride over the rest.
+constexpr int64_t UTRI_MAX_GRID_BLOCKS = (int64_t)1 << 20;
+inline unsigned utri_grid(int64_t n, int tpb) {
+    int64_t b = (n + tpb - 1) / tpb;
+    if (b < 1) b = 1;
+    return (unsigned)(b < UTRI_MAX_GRID_BLOCKS ? b : UTRI_MAX_GRID_BLOCKS);
+}
+#define UTRI_FOR_GRID(i, n)                                                  \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
+
 // ------------------------------------------------------------------ error plumbing
 
 #define UTRI_HIP_TRY(expr)                                 \

@@ -955,20 +955,20 @@ namespace {
 // is world 32 j + 4 r + q, set when the edge is negative there (u >= P+ * 2^32).
 __global__ void k_sign_masks(const double* __restrict__ e_p, int64_t m, uint64_t seed, int ww,
                              uint32_t* __restrict__ masks) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m * ww) return;
-    const int64_t e = t / ww;
-    const int j = (int)(t - e * ww);
-    const double th = e_p[e] * 4294967296.0;
-    uint32_t mk = 0;
-    for (int r = 0; r < 8; r++) {
-        uint32_t x[4];
-        utri_philox((uint32_t)e, (uint32_t)(8 * j + r), 1u, 0u, (uint32_t)seed,
-                    (uint32_t)(seed >> 32), x);
+    UTRI_FOR_GRID(t, m * ww) {
+        const int64_t e = t / ww;
+        const int j = (int)(t - e * ww);
+        const double th = e_p[e] * 4294967296.0;
+        uint32_t mk = 0;
+        for (int r = 0; r < 8; r++) {
+            uint32_t x[4];
+            utri_philox((uint32_t)e, (uint32_t)(8 * j + r), 1u, 0u, (uint32_t)seed,
+                        (uint32_t)(seed >> 32), x);
 #pragma unroll
-        for (int q = 0; q < 4; q++) mk |= ((double)x[q] < th ? 0u : 1u) << (4 * r + q);
+            for (int q = 0; q < 4; q++) mk |= ((double)x[q] < th ? 0u : 1u) << (4 * r + q);
+        }
+        masks[t] = mk;
     }
-    masks[t] = mk;
 }
 
 }  // namespace
@@ -976,7 +976,7 @@ __global__ void k_sign_masks(const double* __restrict__ e_p, int64_t m, uint64_t
 int utri_sign_masks_launch(utri_graph* g, uint64_t seed, int ww, uint32_t* masks, hipStream_t s) {
     const int64_t tot = g->m * ww;
     if (tot == 0) return UTRI_OK;
-    hipLaunchKernelGGL(k_sign_masks, dim3(blocks_for(tot)), dim3(TPB), 0, s, (const double*)g->e_p,
+    hipLaunchKernelGGL(k_sign_masks, dim3(utri_grid(tot, TPB)), dim3(TPB), 0, s, (const double*)g->e_p,
                        g->m, seed, ww, masks);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
