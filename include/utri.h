@@ -115,6 +115,23 @@ int utri_graph_set_p(utri_graph* g, const double* p, int ptr_kind, void* hip_str
  */
 int utri_count(utri_graph* g, double t, int method, int which, int64_t out[2], void* hip_stream);
 
+/*
+ * utri_count without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments,
+ * results and errors as utri_count. Its scratch (row prefixes, work items, counters) lives
+ * in a file-scope device array of UTRI_NOALLOC_SCRATCH_MB MiB that each GPU the library
+ * runs on holds until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call. A graph whose query needs more scratch than that (about
+ * 16 * (2n + 2) + 8 * work items bytes, n <= ~1.5 M vertices at R-MAT density) returns
+ * UTRI_E_CAPACITY before any work is enqueued; UTRI_E_INVALID also when the current HIP
+ * device is not the handle's. Every call on a GPU shares that GPU's array (the call
+ * clears what must start at zero): calls that overlap on one GPU, from any thread,
+ * stream or handle, race. Waits for the stream.
+ */
+#define UTRI_NOALLOC_SCRATCH_MB 64
+int utri_count_noalloc(utri_graph* g, double t, int method, int which, int64_t out[2],
+                       void* hip_stream);
+
 /* Counts at nt thresholds (any order, 1 <= nt <= 64) from one walk at the smallest
  * one: out host int64 [nt][2]. Waits for the stream. */
 int utri_count_batch(utri_graph* g, const double* t, int nt, int method, int64_t* out,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -257,9 +258,76 @@ void apply_cache(utri_graph* g, const char* path) {
     fclose(f);
 }
 
+// ------------------------------------------------------------------ no-allocation counting
+//
+// utri_count_noalloc runs utri_count's kernels on a file-scope device array instead of the
+// handle's hipMalloc'd scratch. In host code `scratch` is only a host-side stand-in for
+// the array: its device address is read once per device with hipGetSymbolAddress (each
+// GPU holds its own copy) and only that address is ever handed to kernels or copies.
+
+constexpr size_t NOALLOC_BYTES = (size_t)UTRI_NOALLOC_SCRATCH_MB << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// Device address of this device's copy of `scratch` (looked up once per device).
+int noalloc_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return UTRI_E_INVALID;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        UTRI_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return UTRI_E_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return UTRI_OK;
+}
+
+// Routes the handle's scratch requests into the arena for the lifetime of this object.
+struct ArenaScope {
+    utri_graph* g;
+    ArenaScope(utri_graph* gg, void* base, size_t bytes) : g(gg) {
+        g->arena = (char*)base;
+        g->arena_bytes = bytes;
+        g->arena_used = 0;
+        for (int i = 0; i < SCR_COUNT; i++) {
+            g->arena_slot[i] = nullptr;
+            g->arena_slot_bytes[i] = 0;
+        }
+    }
+    ~ArenaScope() {
+        g->arena = nullptr;
+        g->arena_bytes = g->arena_used = 0;
+    }
+};
+
 }  // namespace
 
 extern "C" {
+
+int utri_count_noalloc(utri_graph* g, double t, int method, int which, int64_t out[2],
+                       void* hip_stream) {
+    UTRI_TRY(check_graph(g));
+    if (!out || !t_ok(t)) return UTRI_E_INVALID;
+    if (method < UTRI_PLAIN || method > UTRI_PRUNED_L3) return UTRI_E_INVALID;
+    if (which < UTRI_BAL || which > UTRI_BOTH) return UTRI_E_INVALID;
+    if (utri_count_scratch_bound(g, 256) > (int64_t)NOALLOC_BYTES) return UTRI_E_CAPACITY;
+    int dev = -1;
+    UTRI_HIP_TRY(hipGetDevice(&dev));
+    if (dev != g->device) return UTRI_E_INVALID;
+    void* base = nullptr;
+    UTRI_TRY(noalloc_scratch(dev, &base));
+    int64_t r[2] = {0, 0};
+    {
+        ArenaScope scope(g, base, NOALLOC_BYTES);
+        UTRI_TRY(count_impl(g, t, method, r, as_stream(hip_stream)));
+    }
+    out[0] = (which & UTRI_BAL) ? r[0] : 0;
+    out[1] = (which & UTRI_UNBAL) ? r[1] : 0;
+    return UTRI_OK;
+}
 
 const char* utri_strerror(int code) {
     switch (code) {

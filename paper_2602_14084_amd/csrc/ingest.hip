@@ -332,6 +332,20 @@ void utri_note_hip_error(hipError_t e, const char* what, const char* file, int l
 
 int utri_scratch(utri_graph* g, int slot, size_t bytes, void** out) {
     if (bytes == 0) bytes = 16;
+    if (g->arena) {
+        // no-allocation mode: a slot asked for twice in one call keeps its buffer
+        if (g->arena_slot[slot] && g->arena_slot_bytes[slot] >= bytes) {
+            *out = g->arena_slot[slot];
+            return UTRI_OK;
+        }
+        const size_t off = (g->arena_used + 255) & ~(size_t)255;
+        if (off > g->arena_bytes || bytes > g->arena_bytes - off) return UTRI_E_CAPACITY;
+        g->arena_slot[slot] = g->arena + off;
+        g->arena_slot_bytes[slot] = bytes;
+        g->arena_used = off + bytes;
+        *out = g->arena_slot[slot];
+        return UTRI_OK;
+    }
     if (g->scr_bytes[slot] < bytes) {
         if (g->scr[slot]) UTRI_HIP_TRY(hipFree(g->scr[slot]));
         g->scr[slot] = nullptr;

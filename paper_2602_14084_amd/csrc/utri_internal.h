@@ -179,6 +179,13 @@ struct utri_graph {
     void* scr[SCR_COUNT] = {};
     size_t scr_bytes[SCR_COUNT] = {};
     uint64_t scr_gen = 0;  // bumped whenever a scratch buffer is reallocated
+    // No-allocation mode (set for the duration of one call): scratch slots are carved from
+    // this caller-owned device arena instead of hipMalloc; a request that does not fit is
+    // UTRI_E_CAPACITY.
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
+    void* arena_slot[SCR_COUNT] = {};
+    size_t arena_slot_bytes[SCR_COUNT] = {};
 
     // launch shape (set by the autotuner, else defaults)
     int walk_blocks_per_cu = 0;     // 0: the kernel's resident occupancy
@@ -479,6 +486,9 @@ int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const
 int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
                            const int64_t* eids, int64_t k, int64_t* out, hipStream_t s);
 int64_t utri_walk_items_bound(utri_graph* g);
+// Upper bound of the scratch bytes one counting query requests (row prefixes, work items,
+// counters, scan partials, accumulators), with `align` bytes of padding per buffer.
+int64_t utri_count_scratch_bound(const utri_graph* g, int64_t align);
 int utri_grad_launch(utri_graph* g, double* grad, hipStream_t s);
 
 // generic helpers

@@ -885,6 +885,23 @@ static void set_launch_fields(utri_graph* g, WalkParams& wp, const int32_t* len)
     wp.c_dn = dn;
 }
 
+int64_t utri_count_scratch_bound(const utri_graph* g, int64_t align) {
+    const int64_t n = g->n;
+    const int64_t scan_blocks = (n + 1023) / 1024 + 1;  // the scans' block partials
+    const int64_t bytes[] = {
+        4 * (2 * n + 2),                          // oriented and symmetric prefixes
+        4 * (2 * n + 2),                          // light and heavy item counts
+        8 * (2 * n + 2),                          // their offsets
+        8 * (light_bound(g) + heavy_bound(g)),    // work items
+        8 * (int64_t)NITEMS_WORDS,                // item counts, queues, kept totals
+        8 * scan_blocks,                          // scan partials
+        8 * 4,                                    // class counters
+    };
+    int64_t tot = 0;
+    for (int64_t b : bytes) tot += b + align;
+    return tot;
+}
+
 // Slots of the per-item enumeration arrays: one per light item, four per heavy item.
 int64_t utri_walk_items_bound(utri_graph* g) { return light_bound(g) + 4 * heavy_bound(g); }
 

@@ -37,7 +37,7 @@ ABI_FUNCTIONS = [
     "utri_graph_load", "utri_graph_free", "utri_graph_info", "utri_graph_edges",
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
     "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sign_worlds", "utri_sample", "utri_batch", "utri_autotune", "utri_set_walk_order",
-    "utri_walk_stats", "utri_timing", "utri_strerror",
+    "utri_walk_stats", "utri_timing", "utri_strerror", "utri_count_noalloc",
 ]
 
 _lib = None
@@ -66,6 +66,7 @@ def lib():
     L.utri_graph_edges.argtypes = [vp, vp, vp, vp, C.c_int, vp]
     L.utri_graph_set_p.argtypes = [vp, vp, C.c_int, vp]
     L.utri_count.argtypes = [vp, f64, C.c_int, C.c_int, P(i64), vp]
+    L.utri_count_noalloc.argtypes = [vp, f64, C.c_int, C.c_int, P(i64), vp]
     L.utri_count_batch.argtypes = [vp, P(f64), C.c_int, C.c_int, P(i64), vp]
     L.utri_enumerate.argtypes = [vp, f64, C.c_int, C.c_int, vp, i64, vp, i64, P(i64), C.c_int, vp]
     L.utri_expected.argtypes = [vp, P(f64), vp]
@@ -173,6 +174,14 @@ def utri_graph_set_p(h, p, stream=None):
 def utri_count(h, t, method=UTRI_PRUNED, which=UTRI_BOTH, stream=None):
     out = (C.c_int64 * 2)()
     _check(lib().utri_count(h, float(t), method, which, out, _stream(stream)), "utri_count")
+    return int(out[0]), int(out[1])
+
+
+def utri_count_noalloc(h, t, method=UTRI_PRUNED, which=UTRI_BOTH, stream=None):
+    """utri_count on the library's static device scratch (no allocation)."""
+    out = (C.c_int64 * 2)()
+    _check(lib().utri_count_noalloc(h, float(t), method, which, out, _stream(stream)),
+           "utri_count_noalloc")
     return int(out[0]), int(out[1])
 
 
