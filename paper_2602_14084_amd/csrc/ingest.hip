@@ -205,7 +205,7 @@ __global__ void k_scatter_oriented(const int32_t* __restrict__ oflag,
     o_eid[j] = s_eid[i];
 }
 
-// Pack sign(d) and a quantized |d| into the spare high bits of every oriented-row id.
+// Pack a quantized |d| above every oriented-row id and sign(d) into bit 31.
 __global__ void k_pack_oriented(int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                 int64_t m, int idbits, int mb) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,9 +216,9 @@ __global__ void k_pack_oriented(int32_t* __restrict__ o_adj, const double* __res
     // 2^mb - 1, whose bucket [q, q + 1] * 2^-mb still holds it
     uint32_t q = (uint32_t)(fabs(d) * (double)(1u << mb));
     if (q > qmax) q = qmax;
-    const uint32_t sign = d < 0.0 ? 1u : 0u;
-    const uint32_t code = (sign << mb) | q;
-    o_adj[i] = (int32_t)(((uint32_t)o_adj[i]) | (code << idbits));
+    // sign(d) in bit 31 whatever the widths, so one xor of two words gives a product's sign
+    const uint32_t sign = d < 0.0 ? 0x80000000u : 0u;
+    o_adj[i] = (int32_t)(((uint32_t)o_adj[i]) | (q << idbits) | sign);
 }
 
 __global__ void k_oriented_offsets(const int64_t* __restrict__ s_off,

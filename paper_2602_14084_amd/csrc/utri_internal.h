@@ -119,6 +119,7 @@ enum UtriScratch {
     SCR_SIGN_MASK,    // u32 [m][worlds / 32] negative-sign masks of the sign worlds
     SCR_SIGN_CNT,     // u64 [worlds] balanced triangles per sign world
     SCR_TUNE,         // f64 estimates written by the autotuner's sampler trials
+    SCR_RINFO,        // uint2 [n] (row start, kept length) of each vertex at the query's c
     SCR_COUNT
 };
 
@@ -163,18 +164,19 @@ struct utri_graph {
     int64_t h_total = 0;
 
     int64_t* o_off = nullptr;
-    int32_t* o_adj = nullptr;    // packed: id | (sign(d) << (idbits + mb) | q(|d|) << idbits)
+    int32_t* o_adj = nullptr;    // packed: id | q(|d|) << idbits | sign(d) << 31
     double* o_d = nullptr;
     int32_t* o_eid = nullptr;
     // Oriented-row packing. Ids take the low `idbits` bits; when at least three bits are
-    // left, the high bits hold sign(d) and q = min(floor(|d| * 2^mb), 2^mb - 1), so |d|
-    // lies in [q, q + 1] * 2^-mb. Ids are at least 1 (vertex 0 has the lowest rank and is
-    // in no oriented row), so a packed word is never 0.
+    // left, bits idbits .. idbits + mb - 1 hold q = min(floor(|d| * 2^mb), 2^mb - 1), so |d|
+    // lies in [q, q + 1] * 2^-mb, and bit 31 holds sign(d). Ids are at least 1 (vertex 0
+    // has the lowest rank and is in no oriented row), so a packed word is never 0.
     int idbits = 31;
     int code_mb = 0;             // magnitude bits of the code, 0 = no code
     uint32_t idmask = 0x7FFFFFFFu;
 
     uint32_t* d_flags = nullptr;
+    void* rinfo_cur = nullptr;   // the last walk preparation's per-vertex (row start, length)
 
     void* scr[SCR_COUNT] = {};
     size_t scr_bytes[SCR_COUNT] = {};
@@ -406,12 +408,10 @@ struct WalkParams {
     int which = UTRI_BOTH;
     int64_t lb = 0;                     // first enumeration slot of the heavy items (set at launch)
     unsigned long long* qctr = nullptr; // two work-queue counters, zeroed per launch
-    // oriented-row packing (set at launch from the graph) and float bounds of c:
-    // c_dn <= c <= c_up, both FP32
+    // oriented-row packing (set at launch from the graph)
     uint32_t idmask = 0x7FFFFFFFu;
     int idbits = 31;
     int mb = 0;
-    float c_up = 0.f, c_dn = 0.f;
     // SIGN: per-edge negative-sign masks [m][ww] (bit b of word j: world 32 j + b), the
     // oriented rows' edge ids, and the per-world counters
     const int32_t* o_eid = nullptr;
@@ -427,6 +427,7 @@ struct WalkParams {
     const int32_t* s_eid = nullptr;
     const int32_t* slen = nullptr;
     int order = 0;                      // UTRI_ORDER_* (set at launch)
+    const int32_t* o_adj = nullptr;     // packed oriented rows (set at launch)
 };
 
 // Negative-sign masks of `ww` words per edge (worlds 32 ww) for the sign-world walk.

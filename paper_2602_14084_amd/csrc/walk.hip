@@ -18,18 +18,23 @@
 // {x, y} is streamed from x's side (see k_items).
 //
 // GPU mapping (persistent grid, two phases per work-group, atomic work queues):
-//   * long staged rows (len > CAP = 128): one work-group per item (x, CAPH = 1024-entry
-//     chunk, partner range). The chunk of N+(x) is staged in a work-group LDS table and
-//     the four waves take the partners round-robin;
+//   * long staged rows (len > CAP = 128): one work-group per item (x, CAPH = 2048-entry
+//     chunk, partner range); the chunk of N+(x) is staged in a work-group LDS table and
+//     the work-group's waves take the partners round-robin (on R-MAT s23 these items
+//     carry 98% of the streamed ids);
 //   * other staged rows: one wave per item, the row staged in the wave's own table.
-//   Tables are open addressing over buckets of four 32-bit keys, read with one 16-byte
-//   LDS load, at load factor 1/8 (wave) or 1/4 (work-group), so almost every probe ends
-//   in its home bucket. A streamed row is read coalesced, its start and length broadcast
-//   in scalar registers; each lane loads up to eight ids ahead (64 apart) before probing
-//   them, so every wave keeps several loads in flight. Hits are classified from the d
-//   codes packed above the ids; only the few the codes leave undecided read d values.
-//   The classify, count, histogram, fixed-point, enumeration, sign-world and statistics
-//   epilogues are selected at compile time.
+//   A table is open addressing over buckets of four slots with two parallel arrays: the
+//   staged ids (0 = empty) and, per slot, a word holding the entry's d code, its position
+//   in the row and a presence bit. A probe reads one bucket of each with two 16-byte LDS
+//   loads from one address and selects the matching slot's word with four compares; at
+//   the tables' load (at most two entries per bucket on average, one for rows up to half
+//   the capacity) almost every probe ends in its home bucket. A streamed row is read with
+//   buffer loads whose descriptor spans exactly the row, so lanes past its end get 0 (an
+//   id in no table) without a bounds test; each lane has up to eight loads in flight.
+//   Hits are classified from the d codes (staged word and streamed word) with two 24-bit
+//   products against per-row integer thresholds; only the few the codes leave undecided
+//   read the exact d values. The classify, count, histogram, fixed-point, enumeration,
+//   sign-world and statistics epilogues are selected at compile time.
 //
 // Sign worlds (possible-world Monte-Carlo of E): every triangle's three edge ids go to a
 // per-wave LDS queue; a full queue is drained with lanes over world words (world
@@ -46,20 +51,25 @@ using namespace utri_dev;
 namespace {
 
 #ifndef UTRI_WALK_CAPH
-#define UTRI_WALK_CAPH 1024
+#define UTRI_WALK_CAPH 2048
 #endif
-constexpr int CAPH = UTRI_WALK_CAPH;  // source entries per work-group item
-#ifndef UTRI_WALK_SLOTS_WG
-#define UTRI_WALK_SLOTS_WG 4
+#ifndef UTRI_WALK_WAVE_LG
+#define UTRI_WALK_WAVE_LG 7
 #endif
-constexpr int SLOTSH = UTRI_WALK_SLOTS_WG;  // work-group table slots per staged entry
-constexpr int HSH = SLOTSH * CAPH;    // work-group table slots (buckets of 4)
+constexpr int CAPH = UTRI_WALK_CAPH;  // staged entries per work-group item (one chunk of a row)
+constexpr int NW_MAX = 8;             // enumeration slots per heavy item (one per wave)
+constexpr int WAVE_LG = UTRI_WALK_WAVE_LG;  // wave tables: 2^WAVE_LG buckets of 4 slots
+static_assert(CAP <= (4 << WAVE_LG), "wave tables hold CAP entries");
+static_assert(CAPH < 32768, "positions are 15-bit in the table words");
 
+#ifndef UTRI_WALK_NW
+#define UTRI_WALK_NW 8             // waves per work-group of the counting walks
+#endif
+#ifndef UTRI_WALK_LGH
+#define UTRI_WALK_LGH 10           // log2 of the work-group table's buckets
+#endif
 #ifndef UTRI_WALK_UNR_MAX
 #define UTRI_WALK_UNR_MAX 8        // loads in flight per lane on long streamed rows
-#endif
-#ifndef UTRI_WALK_DYNAMIC
-#define UTRI_WALK_DYNAMIC 1        // 1: items handed out by atomic work queues; 0: static stride
 #endif
 #ifndef UTRI_WALK_PR
 #define UTRI_WALK_PR 1024          // symmetric-row entries (partners) per item
@@ -69,21 +79,123 @@ constexpr int PR = UTRI_WALK_PR;
 #define UTRI_WALK_SHORTER 1        // 1: each edge streams the shorter kept row; 0: always N+(v)
 #endif
 
+// Launch geometry of a walk kernel: NW waves per work-group, a work-group table of 2^LGH
+// buckets and wave tables of 2^WLG buckets, four slots per bucket.
+template <int NW_, int LGH_, int WLG_>
+struct Geom {
+    static constexpr int NW = NW_;
+    static constexpr int TPBW = NW_ * UTRI_WAVE;
+    static constexpr int LGH = LGH_;
+    static constexpr int WLG = WLG_;
+};
+using GeomWalk = Geom<UTRI_WALK_NW, UTRI_WALK_LGH, WAVE_LG>;  // the standalone walks
+using GeomBatch = Geom<WPB, 10, 7>;  // the fused batch (the sampler's block size)
+static_assert(UTRI_WALK_NW <= NW_MAX && WPB <= NW_MAX, "enumeration slots");
 
 inline int blocks_for(int64_t n) { return (int)((n + TPB - 1) / TPB); }
 
-struct BlockLds {
-    alignas(16) int32_t key[HSH];
-    uint16_t pos[HSH];
+// A table keeps, per slot, the staged id (0 = empty) and a word: sign of d_uw in bit 31,
+// QB = 15 magnitude bits of |d_uw| (floor(|d_uw| * 2^15), at most 2^15 - 1, from the exact
+// d at staging) in bits 16..30, a presence bit (bit 15, so a word is never 0) and the
+// entry's position in the staged chunk in bits 0..14.
+constexpr int QB = 15;
+constexpr uint32_t W_PRESENT = 1u << 15;
+constexpr uint32_t W_POS = (1u << 15) - 1u;
+
+template <class G>
+struct WaveTab {
+    alignas(16) uint32_t key[4 << G::WLG];
+    alignas(16) uint32_t word[4 << G::WLG];
+};
+template <class G>
+struct BlockTab {
+    alignas(16) uint32_t key[4 << G::LGH];
+    alignas(16) uint32_t word[4 << G::LGH];
+};
+template <class G>
+union WalkShared {
+    WaveTab<G> wave[G::NW];
+    BlockTab<G> block;
 };
 
-union WalkShared {
-    WalkLds wave[WPB];
-    BlockLds block;
+// Table of a staged chunk: key array (its word array follows at WOFF slots), bucket mask,
+// where the staged entries sit in o_adj / o_d, perm[u] (enumeration) and the chunk index.
+struct TabRef {
+    const uint32_t* key;
+    uint32_t bmask;
+    int64_t src_base;
+    int32_t pu;
+    int chunk;
 };
-static_assert(CAPH >= CAP && CAPH <= 65536 && (CAPH & (CAPH - 1)) == 0 &&
-                  (SLOTSH & (SLOTSH - 1)) == 0,
-              "work-group chunks hold every long row's chunk; table sizes are powers of two");
+
+// log2 of the bucket count for cl staged entries: 2^lg >= 2 cl (at most two entries per
+// bucket of four on average), at least 2 buckets, at most 2^max_lg
+__device__ __forceinline__ int tab_lg(int cl, int max_lg) {
+    int lg = 1;
+    while (lg < max_lg && (1 << lg) < 2 * cl) lg++;
+    return lg;
+}
+
+// Clear the first 2^lg buckets of a table (keys and words).
+template <int WOFF>
+__device__ __forceinline__ void tab_clear(uint32_t* key, int lg, int tid, int nth) {
+    const int n4 = 1 << lg;  // buckets = uint4 stores per array
+    uint4* k4 = reinterpret_cast<uint4*>(key);
+    uint4* w4 = reinterpret_cast<uint4*>(key + WOFF);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < n4; i += nth) {
+        k4[i] = z;
+        w4[i] = z;
+    }
+}
+
+// Stage cl entries o_adj[base ..] / o_d[base ..] (ids of at least 1) into a table of
+// bmask + 1 buckets: each entry takes the first free slot from its home bucket (its id's
+// low bits: ids rank vertices by degree with ties broken by a mixed id, so they spread
+// over the buckets) onwards; slots of a bucket fill in order, so a bucket whose last key
+// is 0 has room and ends a probe.
+template <int WOFF>
+__device__ __forceinline__ void tab_stage(uint32_t* key, const int32_t* __restrict__ o_adj,
+                                          const double* __restrict__ o_d, int64_t base, int cl,
+                                          uint32_t bmask, int tid, int nth, uint32_t idmask) {
+    for (int j = tid; j < cl; j += nth) {
+        const uint32_t pw = (uint32_t)o_adj[base + j];
+        const uint32_t id = pw & idmask;
+        const double d = o_d[base + j];
+        // floor (exact: a power-of-two scaling), |d| = 1 clamped into the top code
+        const uint32_t q = min((uint32_t)(fabs(d) * (double)(1u << QB)), (1u << QB) - 1u);
+        const uint32_t word = (d < 0.0 ? 0x80000000u : 0u) | (q << 16) | W_PRESENT | (uint32_t)j;
+        uint32_t b = id & bmask;
+        for (;;) {
+            int s = 0;
+            while (s < 4 && atomicCAS(&key[4 * b + s], 0u, id) != 0u) s++;
+            if (s < 4) {
+                key[WOFF + 4 * b + s] = word;
+                break;
+            }
+            b = (b + 1) & bmask;
+        }
+    }
+}
+
+// The word of id w, 0 if absent. Lanes past a streamed row's end probe w = 0, which only
+// matches empty slots, whose words are 0.
+template <int WOFF>
+__device__ __forceinline__ uint32_t tab_find(const uint32_t* key, uint32_t bmask, uint32_t w) {
+    uint32_t b = w & bmask;
+    uint32_t r;
+    for (;;) {
+        const uint4 k = *reinterpret_cast<const uint4*>(key + 4 * b);
+        const uint4 d = *reinterpret_cast<const uint4*>(key + WOFF + 4 * b);
+        r = (k.w == w) ? d.w : 0u;
+        r = (k.z == w) ? d.z : r;
+        r = (k.y == w) ? d.y : r;
+        r = (k.x == w) ? d.x : r;
+        if (r != 0u || k.w == 0u) break;
+        b = (b + 1) & bmask;
+    }
+    return r;
+}
 
 // Items. Every vertex x with a kept oriented row of len >= 2 stages (chunks of) N+(x) as a
 // table and streams, for each partner y (a kept neighbour of x, in ranges of PR entries of
@@ -162,11 +274,14 @@ __device__ __forceinline__ int32_t kept_prefix(const int64_t* __restrict__ off,
     return (int32_t)(lo - a);
 }
 
+// Also writes rinfo[v] = (start of N+(v) in o_adj, kept length): what a partner scan reads
+// about each partner, in one 8-byte load (m < 2^31, so row starts fit 32 bits).
 __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restrict__ dd,
                          const int64_t* __restrict__ soff, const double* __restrict__ sd,
                          int64_t n, double c, int32_t* __restrict__ len,
                          int32_t* __restrict__ slen, int32_t* __restrict__ lcnt,
-                         int32_t* __restrict__ hcnt, unsigned long long* __restrict__ kept) {
+                         int32_t* __restrict__ hcnt, unsigned long long* __restrict__ kept,
+                         uint2* __restrict__ rinfo) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t L = 0, SL = 0;
     if (v < n) {
@@ -192,6 +307,7 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
     if (v >= n) return;
     len[v] = L;
     slen[v] = SL;
+    rinfo[v] = make_uint2((uint32_t)off[v], (uint32_t)L);
     const int nr = partner_ranges(SL);
     lcnt[v] = (L >= 2 && L <= CAP) ? nr : 0;
     hcnt[v] = (L > CAP) ? ((L + CAPH - 1) / CAPH) * nr : 0;
@@ -225,13 +341,14 @@ struct WalkLaneState {
     uint32_t bs[SIGN_K] = {};      // SIGN: bit planes of this lane's 32 world counters
     uint32_t npass = 0;            // SIGN: additions since the last flush (wave-uniform)
     int qn = 0;                    // SIGN: queued triangles (wave-uniform)
+    int dn = 0;                    // COUNT / ENUM_COUNT: deferred hits queued (wave-uniform)
 };
 
 // SIGN: per-wave queue of triangles as their three edge ids
 struct SignQueue {
     int32_t e[3][SIGN_Q];
 };
-__shared__ SignQueue sign_q[WPB];
+__shared__ SignQueue sign_q[NW_MAX];
 
 // Add this lane's 32 counters into the per-world totals and clear them.
 __device__ __forceinline__ void sign_flush(const WalkParams& wp, WalkLaneState& st) {
@@ -279,39 +396,30 @@ __device__ __forceinline__ void sign_drain(const WalkParams& wp, WalkLaneState& 
     utri_wave_sync();
 }
 
-// The staged source chunk and the current pair (u, v).
-struct RowCtx {
-    const int32_t* key;  // 2^lg buckets of 4 slots; slots of a bucket fill in order
-    const uint16_t* pos;
-    int lg;
-    uint32_t mask;       // bucket index mask
-    int64_t src_base;   // o_off[u] + chunk start: position of hash hits in o_adj / o_d
-    int32_t pu;         // perm[u] (enumeration)
-    int chunk;
-};
-
-// Per-row integer thresholds of the code decision. With A = |d_uv| and code magnitudes
-// qb (of d_uw) and qc (of d_vw), |s| lies in [A * P0, A * P1] * 2^-2mb with P0 = qb * qc and
-// P1 = (qb + 1) * (qc + 1). With K = c * 2^2mb / A:
+// Per-row integer thresholds of the code decision. With A = |d_uv|, qb the 15-bit code of
+// |d_uw| (table word) and qc the mb-bit code of |d_vw| (streamed word), |s| lies in
+// [A * P0, A * P1] * 2^-(15 + mb) with P0 = qb * qc and P1 = (qb + 1) * (qc + 1). With
+// K = c * 2^(15 + mb) / A:
 //   P0 >= khi = floor(K (1 + 2^-40)) + 1   =>  |s| > c  (balanced if s < 0, else unbalanced)
 //   P1 <= klo = floor(K (1 - 2^-40))       =>  |s| < c  (neither)
 // The 2^-40 margins exceed the roundings of K and the 2^-51 gap between the real product
-// and the FP64 s of the exact rule. A = 0 rows are left to the exact rule.
+// and the FP64 s of the exact rule, so exact ties always go to the exact rule. A = 0 rows
+// are left to the exact rule. rsign holds sign(d_uv) in bit 31, so bit 31 of (table word
+// ^ streamed word ^ rsign) is sign(s).
 struct CodeRow {
-    uint32_t khi, klo;
-    bool neg_a;
+    uint32_t khi, klo, rsign;
 };
 
 __device__ __forceinline__ CodeRow code_row(const WalkParams& wp, double duv) {
     CodeRow r;
     const double a = fabs(duv);
-    r.neg_a = duv < 0.0;
+    r.rsign = duv < 0.0 ? 0x80000000u : 0u;
     if (!(a > 0.0) || wp.mb == 0) {
         r.khi = 0xFFFFFFFFu;
         r.klo = 0u;
         return r;
     }
-    const double K = ldexp(wp.c, 2 * wp.mb) / a;
+    const double K = ldexp(wp.c, QB + wp.mb) / a;
     const double hi = floor(K * (1.0 + 0x1p-40)) + 1.0;
     const double lo = floor(K * (1.0 - 0x1p-40));
     r.khi = hi >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)hi;
@@ -319,167 +427,233 @@ __device__ __forceinline__ CodeRow code_row(const WalkParams& wp, double duv) {
     return r;
 }
 
-// 1 balanced, 2 unbalanced, 0 neither, -1 undecided (see code_row)
-__device__ __forceinline__ int code_decide(const WalkParams& wp, const CodeRow& r, uint32_t cu,
-                                           uint32_t cv) {
-    const uint32_t mmask = (1u << wp.mb) - 1u;
-    const uint32_t qb = cu & mmask, qc = cv & mmask;
-    // operands are at most 2^15: the 24-bit multiplier is exact (its result is a signed int)
-    uint32_t p0 = (uint32_t)__umul24(qb, qc), p1 = (uint32_t)__umul24(qb + 1u, qc + 1u);
-    // both products in registers first, so the selects below stay selects (the caller
-    // evaluates this on every lane; branches would only add exec-mask work)
-    asm volatile("" : "+v"(p0), "+v"(p1));
-    const int neg = (int)((r.neg_a ? 1u : 0u) ^ (((cu ^ cv) >> wp.mb) & 1u));
-    const int dec = (p1 <= r.klo) ? 0 : -1;
-    return (p0 >= r.khi) ? 2 - neg : dec;
+// Hits the codes leave undecided (counting walks): queued per wave as (position of d_vw in
+// o_d, staged position | partner slot << 15) and decided by the exact rule in batches, so
+// a wave waits for their d loads once per batch instead of once per strip. The queue is
+// drained between partner rows once it holds more than DQ_DRAIN entries and whenever the
+// partners' d values (registers of the current batch of 64 partners) are about to change;
+// a strip whose hits do not fit decides them at once.
+constexpr int DQ_CAP = 96;
+constexpr int DQ_DRAIN = 48;
+struct DeferQueue {
+    uint32_t vw[DQ_CAP];
+    uint32_t ps[DQ_CAP];
+};
+__shared__ DeferQueue defer_q[NW_MAX];
+
+// Decide the queued hits exactly and count them; duv_lanes: d_xy of the batch's partners
+// on their lanes, src_base: position of the staged chunk in o_d.
+__device__ __forceinline__ void defer_drain(const WalkParams& wp, const double* __restrict__ o_d,
+                                            int64_t src_base, double duv_lanes, WalkLaneState& st) {
+    DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+    utri_wave_sync();
+    for (int e0 = 0; e0 < st.dn; e0 += UTRI_WAVE) {
+        const int e = e0 + utri_lane();
+        const bool live = e < st.dn;
+        const uint32_t ps = live ? Q.ps[e] : 0u;
+        const uint32_t vw = live ? Q.vw[e] : 0u;
+        const double duv = __shfl(duv_lanes, (int)(ps >> 15), UTRI_WAVE);
+        if (live) {
+            const double s = utri_tri_s(duv, o_d[src_base + (ps & W_POS)], o_d[vw]);
+            st.nb32 += (s <= -wp.c) ? 1u : 0u;
+            st.nu32 += (s > wp.c) ? 1u : 0u;
+        }
+    }
+    st.dn = 0;
+    utri_wave_sync();
 }
 
 // Stream the kept target row [ovs, ovs + lvs) of v, probing every entry in the table.
-// Row entries and table keys are packed words: id in the low bits, d code above.
-template <int MODE, int UNR>
-__device__ __forceinline__ void stream_row(const WalkParams& wp, const int32_t* __restrict__ o_adj,
-                                           const double* __restrict__ o_d,
-                                           const int32_t* __restrict__ perm, const RowCtx& R,
-                                           int64_t ovs, int lvs, double duvs, int32_t pv,
-                                           const CodeRow& cr,
-                                           HistLds* H, WalkLaneState& st, int64_t& run_b,
-                                           int64_t& run_u) {
-    const int lane = utri_lane();
+// Row entries are packed words (id in the low idbits bits, mb-bit d code above, sign(d)
+// in bit 31); table words carry the staged entry's code and position. si: the partner's
+// slot in its batch of 64 (deferred hits); duv_lanes: the batch's d_xy on their lanes.
 #ifndef UTRI_WALK_CODES
 #define UTRI_WALK_CODES 1
 #endif
+
+// A buffer descriptor spanning exactly the kept row [ovs, ovs + lvs) of o_adj: loads at or
+// past its end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const WalkParams& wp, int64_t ovs,
+                                                           int lvs) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(wp.o_adj + ovs), (short)0, lvs * 4,
+                                             0x00020000);
+}
+
+template <int UNR>
+__device__ __forceinline__ void load_strips(__amdgpu_buffer_rsrc_t rs, int j0, uint32_t (&pw)[UNR]) {
+    const int lane = utri_lane();
+#pragma unroll
+    for (int k = 0; k < UNR; k++)
+        pw[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (j0 + k * UTRI_WAVE + lane) * 4,
+                                                               0, 0);
+}
+
+// Probe the UNR loaded strips pw (row positions j0 + 64 k + lane) of the row [ovs, ovs + lvs)
+// and apply the mode's epilogue to every hit.
+template <int MODE, int UNR, int WOFF>
+__device__ __forceinline__ void probe_strips(const WalkParams& wp, const double* __restrict__ o_d,
+                                             const int32_t* __restrict__ perm, const TabRef& R,
+                                             const uint32_t (&pw)[UNR], int j0, int64_t ovs,
+                                             int lvs, double duvs, int32_t pv, const CodeRow& cr,
+                                             int si, HistLds* H, WalkLaneState& st,
+                                             int64_t& run_b, int64_t& run_u) {
+    const int lane = utri_lane();
     constexpr bool kCoded = UTRI_WALK_CODES && (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
                                                 MODE == WALK_ENUM_FILL);
-    // wave-uniform row base; in-row byte offsets are 32-bit (oriented rows under Node
-    // Order are far shorter than 2^30 entries), so loads take the scalar-base form with the
-    // strip offsets as immediates. Lanes past the row end are masked off (reading on into
-    // the next rows cost 17% more HBM bytes for no faster walk); the id array is still
-    // padded by UTRI_ROW_PAD entries so that every strip address is inside it.
-    static_assert(UNR * UTRI_WAVE <= UTRI_ROW_PAD, "row streams stay inside the padding");
-    const char* rowb = (const char*)((const uint32_t*)o_adj + ovs);
+    constexpr bool kDefer = MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT;
+    const uint32_t qm = (1u << wp.mb) - 1u;
     const double* rowd = o_d + ovs;
-    for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
-        // all UNR loads are issued before any probe
-        uint32_t pw[UNR];
-        const char* lb = rowb + (((uint32_t)(j0 + lane)) << 2);
-#pragma unroll
-        for (int k = 0; k < UNR; k++)
-            pw[k] = (j0 + k * UTRI_WAVE + lane < lvs) ? *(const uint32_t*)(lb + k * 4 * UTRI_WAVE) : 0u;
+    {
 #pragma unroll
         for (int k = 0; k < UNR; k++) {
             // strips past the row end hold no entries (wave-uniform exit)
             if (k > 0 && j0 + k * UTRI_WAVE >= lvs) break;
             const int j = j0 + k * UTRI_WAVE + lane;
             const uint32_t w = pw[k] & wp.idmask;
-            bool is_b = false, is_u = false;
-            bool sg = false;
-            int32_t euw = 0, evw = 0;
-            // kk: the matching packed key, 0 if none; h: its slot
-            int h;
-            const int kk = bucket_find(R.key, R.lg, R.mask, w, wp.idmask, h);
-            if (j < lvs && kk != 0) {
-                const uint32_t hkey = (uint32_t)kk;
-                if (MODE == WALK_STATS) {
-                    st.tri++;
-                } else if (MODE == WALK_SIGN) {
-                    sg = true;
-                    euw = wp.o_eid[R.src_base + R.pos[h]];
-                    evw = wp.o_eid[ovs + j];
-                } else {
-                    int dec = -1;
-                    if (kCoded && wp.mb > 0)
-                        dec = code_decide(wp, cr, hkey >> wp.idbits, pw[k] >> wp.idbits);
-                    if (dec < 0) {
-                        const int hit = R.pos[h];  // only the exact rule reads d_uw
-                        const double s = utri_tri_s(duvs, o_d[R.src_base + hit], rowd[j]);
-                        dec = (s <= -wp.c) ? 1 : ((s > wp.c) ? 2 : 0);
-                        if (!kCoded) {
-                            if (MODE == WALK_HIST) {
-                                bool bal;
-                                const int bin = thresh_bin(s, bal);
-                                if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
-                            } else if (MODE == WALK_EXPECTED) {
-                                const int64_t t = utri_fix62(s);
-                                st.tri++;
-                                st.slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
-                                st.shi += (t >> 32);
+            const uint32_t r = tab_find<WOFF>(R.key, R.bmask, w);
+            const bool found = r != 0u;
+            if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT || MODE == WALK_ENUM_FILL) {
+                bool is_b = false, is_u = false;
+                bool und = found;
+                if (kCoded) {
+                    const uint32_t qb = (r >> 16) & ((1u << QB) - 1u);
+                    const uint32_t qc = (pw[k] >> wp.idbits) & qm;
+                    const uint32_t p0 = __umul24(qb, qc);
+                    const uint32_t t1 = p0 + qb + qc;  // (qb + 1)(qc + 1) - 1
+                    const bool cls = p0 >= cr.khi;
+                    const bool nei = t1 < cr.klo;
+                    const bool neg = (int32_t)(r ^ pw[k] ^ cr.rsign) < 0;
+                    is_b = found && cls && neg;
+                    is_u = found && cls && !neg;
+                    und = found && !cls && !nei;
+                }
+                if (kDefer) {
+                    st.nb32 += is_b ? 1u : 0u;
+                    st.nu32 += is_u ? 1u : 0u;
+                    const uint64_t um = __ballot(und);
+                    if (um) {
+                        const int nq = __popcll(um);
+                        if (st.dn + nq <= DQ_CAP) {
+                            if (und) {
+                                DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+                                const int slot = st.dn + __popcll(um & __lanemask_lt());
+                                Q.vw[slot] = (uint32_t)(ovs + j);
+                                Q.ps[slot] = (r & W_POS) | ((uint32_t)si << 15);
                             }
+                            st.dn += nq;
+                        } else if (und) {
+                            const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
+                            st.nb32 += (s <= -wp.c) ? 1u : 0u;
+                            st.nu32 += (s > wp.c) ? 1u : 0u;
                         }
                     }
-                    if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) {
-                        // dec is 0, 1 or 2 here: bit 0 counts balanced, bit 1 unbalanced
-                        st.nb32 += (uint32_t)dec & 1u;
-                        st.nu32 += (uint32_t)dec >> 1;
-                    } else if (MODE == WALK_ENUM_FILL) {
-                        is_b = (dec == 1) && (wp.which & UTRI_BAL);
-                        is_u = (dec == 2) && (wp.which & UTRI_UNBAL);
+                } else {
+                    if (und) {
+                        // the exact FP64 rule reads d_uw and d_vw
+                        const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
+                        is_b = s <= -wp.c;
+                        is_u = s > wp.c;
                     }
+                    is_b = is_b && (wp.which & UTRI_BAL);
+                    is_u = is_u && (wp.which & UTRI_UNBAL);
+                    const uint64_t mb_ = __ballot(is_b);
+                    const uint64_t mu_ = __ballot(is_u);
+                    if (is_b || is_u) {
+                        int32_t a = R.pu, b = pv, c = perm[w], t;
+                        if (b < a) { t = a; a = b; b = t; }
+                        if (c < b) { t = b; b = c; c = t; }
+                        if (b < a) { t = a; a = b; b = t; }
+                        const uint64_t lt = __lanemask_lt();
+                        int32_t* dst;
+                        int64_t slot;
+                        if (is_b) { dst = wp.out_bal; slot = run_b + __popcll(mb_ & lt); }
+                        else      { dst = wp.out_unbal; slot = run_u + __popcll(mu_ & lt); }
+                        dst[3 * slot] = a;
+                        dst[3 * slot + 1] = b;
+                        dst[3 * slot + 2] = c;
+                    }
+                    run_b += __popcll(mb_);
+                    run_u += __popcll(mu_);
                 }
-            }
-            if (MODE == WALK_SIGN) {
-                // queue this sub-strip's triangles (pv carries the edge id of u -> v)
-                const uint64_t hm = __ballot(sg);
+            } else if (MODE == WALK_STATS) {
+                if (found) st.tri++;
+            } else if (MODE == WALK_SIGN) {
+                // queue this strip's triangles (pv carries the edge id of u -> v)
+                const uint64_t hm = __ballot(found);
                 if (hm) {
-                    if (sg) {
+                    if (found) {
                         SignQueue& Q = sign_q[threadIdx.x / UTRI_WAVE];
                         const int slot = st.qn + __popcll(hm & __lanemask_lt());
                         Q.e[0][slot] = pv;
-                        Q.e[1][slot] = euw;
-                        Q.e[2][slot] = evw;
+                        Q.e[1][slot] = wp.o_eid[R.src_base + (r & W_POS)];
+                        Q.e[2][slot] = wp.o_eid[ovs + j];
                     }
                     st.qn += __popcll(hm);
                     if (st.qn >= SIGN_Q - UTRI_WAVE) sign_drain(wp, st);
                 }
-            }
-            if (MODE == WALK_ENUM_FILL) {
-                const uint64_t mb = __ballot(is_b);
-                const uint64_t mu = __ballot(is_u);
-                if (is_b || is_u) {
-                    int32_t a = R.pu, b = pv, c = perm[w], t;
-                    if (b < a) { t = a; a = b; b = t; }
-                    if (c < b) { t = b; b = c; c = t; }
-                    if (b < a) { t = a; a = b; b = t; }
-                    const uint64_t lt = __lanemask_lt();
-                    int32_t* dst;
-                    int64_t slot;
-                    if (is_b) { dst = wp.out_bal; slot = run_b + __popcll(mb & lt); }
-                    else      { dst = wp.out_unbal; slot = run_u + __popcll(mu & lt); }
-                    dst[3 * slot] = a;
-                    dst[3 * slot + 1] = b;
-                    dst[3 * slot + 2] = c;
+            } else if (found) {
+                const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
+                if (MODE == WALK_HIST) {
+                    bool bal;
+                    const int bin = thresh_bin(s, bal);
+                    if (bin > 0) atomicAdd(&H->hist[bal ? 0 : 1][bin], 1ull);
+                } else if (MODE == WALK_EXPECTED) {
+                    const int64_t t = utri_fix62(s);
+                    st.tri++;
+                    st.slo += (uint64_t)(uint32_t)(t & 0xFFFFFFFFll);
+                    st.shi += (t >> 32);
                 }
-                run_b += __popcll(mb);
-                run_u += __popcll(mu);
             }
         }
     }
-    if (MODE == WALK_STATS && lane == 0) {
+}
+
+// Stream the kept target row [ovs, ovs + lvs) of v, UNR strips of loads in flight.
+template <int MODE, int UNR, int WOFF>
+__device__ __forceinline__ void stream_row(const WalkParams& wp, const double* __restrict__ o_d,
+                                           const int32_t* __restrict__ perm, const TabRef& R,
+                                           int64_t ovs, int lvs, double duvs, int32_t pv,
+                                           const CodeRow& cr, int si, double duv_lanes,
+                                           HistLds* H, WalkLaneState& st, int64_t& run_b,
+                                           int64_t& run_u) {
+    (void)duv_lanes;
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(wp, ovs, lvs);
+    for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
+        uint32_t pw[UNR];
+        load_strips<UNR>(rs, j0, pw);  // all UNR loads are issued before any probe
+        probe_strips<MODE, UNR, WOFF>(wp, o_d, perm, R, pw, j0, ovs, lvs, duvs, pv, cr, si, H, st,
+                                      run_b, run_u);
+    }
+    if (MODE == WALK_STATS && utri_lane() == 0) {
         st.wt_all += (uint64_t)lvs;
         if (R.chunk == 0) st.wt += (uint64_t)lvs;
     }
 }
 
-template <int MODE>
-__device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* __restrict__ o_adj,
-                                           const double* __restrict__ o_d,
-                                           const int32_t* __restrict__ perm, const RowCtx& R,
+template <int MODE, int WOFF>
+__device__ __forceinline__ void stream_any(const WalkParams& wp, const double* __restrict__ o_d,
+                                           const int32_t* __restrict__ perm, const TabRef& R,
                                            int64_t ovs, int lvs, double duvs, int32_t pv,
-                                           const CodeRow& cr,
+                                           const CodeRow& cr, int si, double duv_lanes,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
 #if UTRI_WALK_UNR_MAX >= 8
     // the sign-world walk keeps its counter planes in registers: eight loads ahead would
     // spill them
     if (MODE != WALK_SIGN && lvs > 4 * UTRI_WAVE)
-        stream_row<MODE, 8>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
+        stream_row<MODE, 8, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+                                  run_b, run_u);
     else
 #endif
     if (lvs > 2 * UTRI_WAVE)
-        stream_row<MODE, 4>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
+        stream_row<MODE, 4, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+                                  run_b, run_u);
     else if (lvs > UTRI_WAVE)
-        stream_row<MODE, 2>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
+        stream_row<MODE, 2, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+                                  run_b, run_u);
     else
-        stream_row<MODE, 1>(wp, o_adj, o_d, perm, R, ovs, lvs, duvs, pv, cr, H, st, run_b, run_u);
+        stream_row<MODE, 1, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+                                  run_b, run_u);
 }
 
 // Load, on lane i, partner y = entry sb + i0 + i of the kept symmetric row of x (np
@@ -487,34 +661,37 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const int32_t* 
 // item streams (0 when the edge {x, y} is streamed from y's side, see k_items), d_xy and
 // the edge id (sign worlds).
 template <int MODE, bool shorter>
-__device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_t* __restrict__ o_off,
-                                              const int32_t* __restrict__ o_adj,
+__device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
-                                              const int32_t* __restrict__ len, int x,
-                                              int Lx, int64_t sb, int np, int i0,
-                                              double dmax_chunk, int& y, int64_t& oy, int& ly,
-                                              double& dxy, int32_t& exy, CodeRow& cr) {
+                                              const uint2* __restrict__ rinfo, int x, int Lx,
+                                              int64_t sb, int np, int i0, double dmax_chunk,
+                                              int& y, int64_t& oy, int& ly, double& dxy,
+                                              int32_t& exy, CodeRow& cr) {
     const int i = i0 + utri_lane();
     ly = 0; y = 0; oy = 0; dxy = 0.0; exy = 0;
-    cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.neg_a = false;
+    cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.rsign = 0u;
     if (i < np) {
         // shorter: entry of x's kept symmetric row; else: entry of N+(x) itself
         y = shorter ? wp.s_adj[sb + i] : (int)((uint32_t)o_adj[sb + i] & wp.idmask);
-        const int L = len[y];
+        const uint2 ri = rinfo[y];
+        const int L = (int)ri.y;
         const bool mine = !shorter || ((y > x) ? (L <= Lx) : (L < Lx));
         if (mine && L > 0) {
             dxy = shorter ? wp.s_d[sb + i] : o_d[sb + i];
-            oy = o_off[y];
+            oy = (int64_t)ri.x;
             ly = L;
             if (wp.lemma3) {
-                // Lemma 3: keep w only if |d_yw| * (|d_xy| * max|d_xw|) >= c (with slack)
+                // Lemma 3: keep w only if |d_yw| * (|d_xy| * max|d_xw|) >= c (with slack);
+                // the row is in |d| order, so nothing is cut when its last entry passes
                 const double P = __dmul_rn(fabs(dxy), dmax_chunk);
-                int a = 0, b = ly;
-                while (a < b) {
-                    const int mid = (a + b) >> 1;
-                    if (__dmul_rn(fabs(o_d[oy + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
+                if (__dmul_rn(fabs(o_d[oy + ly - 1]), P) < wp.c_l3) {
+                    int a = 0, b = ly;
+                    while (a < b) {
+                        const int mid = (a + b) >> 1;
+                        if (__dmul_rn(fabs(o_d[oy + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
+                    }
+                    ly = a;
                 }
-                ly = a;
             }
             cr = code_row(wp, dxy);
             if (MODE == WALK_SIGN) exy = shorter ? wp.s_eid[sb + i] : wp.o_eid[sb + i];
@@ -522,16 +699,59 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int64_
     }
 }
 
+#ifndef UTRI_WALK_MIN_WAVES
+#define UTRI_WALK_MIN_WAVES 8      // waves per SIMD the register allocation must allow
+#endif
 
+// Stream every partner row of one partner range of an item through the staged table;
+// partner si of a batch of 64 goes to the wave with si % nparts == part.
+template <int MODE, bool shorter, int WOFF>
+__device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_t* __restrict__ o_adj,
+                                              const double* __restrict__ o_d,
+                                              const uint2* __restrict__ rinfo,
+                                              const int32_t* __restrict__ perm, const TabRef& R,
+                                              int u, int Lu, int64_t sb, int np, double dmax_chunk,
+                                              int part, int nparts, HistLds* H, WalkLaneState& st,
+                                              int64_t& run_b, int64_t& run_u) {
+    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE) {
+        int v, lv;
+        int64_t ov;
+        double duv;
+        int32_t euv;
+        CodeRow cr;
+        load_partners<MODE, shorter>(wp, o_adj, o_d, rinfo, u, Lu, sb, np, i0, dmax_chunk, v, ov,
+                                     lv, duv, euv, cr);
+        const int nv = min(UTRI_WAVE, np - i0);
+        // lane by lane (a loop over the set bits of a ballot made the sign-world walk slower
+        // and the others no faster)
+        for (int si = part; si < nv; si += nparts) {
+            const int lvs = bcast_i32(lv, si);
+            if (lvs == 0) continue;
+            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
+                               : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
+            const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
+                              (uint32_t)bcast_i32((int)cr.klo, si),
+                              (uint32_t)bcast_i32((int)cr.rsign, si)};
+            stream_any<MODE, WOFF>(wp, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
+                                   pv, crs, si, duv, H, st, run_b, run_u);
+            if ((MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) && st.dn > DQ_DRAIN)
+                defer_drain(wp, o_d, R.src_base, duv, st);
+        }
+        // deferred hits use this batch's d_xy
+        if ((MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) && st.dn > 0)
+            defer_drain(wp, o_d, R.src_base, duv, st);
+    }
+}
 
 // Wave item: vertex u with 2 <= len <= CAP, N+(u) staged in the wave's own table, and
 // one range of its partners.
-template <int MODE, bool shorter>
+template <int MODE, bool shorter, class G>
 __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
-                               const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                               int64_t item, int64_t it, WalkLds& L, HistLds* H,
-                               WalkLaneState& st) {
+                               const int32_t* __restrict__ len, const uint2* __restrict__ rinfo,
+                               const int32_t* __restrict__ perm, int64_t item, int64_t it,
+                               WaveTab<G>& L, HistLds* H, WalkLaneState& st) {
+    constexpr int WOFF = 4 << G::WLG;
     const int lane = utri_lane();
     const int u = item_vertex(item);
     const int rg = item_range(item);
@@ -540,40 +760,17 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * PR : ou;
     const int np = shorter ? min(PR, wp.slen[u] - rg * PR) : (rg == 0 ? Lu : 0);
     if (np <= 0) return;  // (the enumeration slots start zeroed)
-    const int lg = table_lg(Lu, SLOTS);
-    const int nbk = 1 << lg;  // buckets
-    for (int i = lane; i < 4 * nbk; i += UTRI_WAVE) L.key[i] = 0;
+    const int lg = tab_lg(Lu, G::WLG);
+    tab_clear<WOFF>(L.key, lg, lane, UTRI_WAVE);
     utri_wave_sync();
-    stage_table(o_adj, ou, Lu, L.key, L.pos, lg, lane, UTRI_WAVE, wp.idmask);
+    tab_stage<WOFF>(L.key, o_adj, o_d, ou, Lu, (1u << lg) - 1u, lane, UTRI_WAVE, wp.idmask);
     utri_wave_sync();
-    RowCtx R{L.key, L.pos, lg, (uint32_t)(nbk - 1), ou,
-             (MODE == WALK_ENUM_FILL) ? perm[u] : 0, 0};
+    const TabRef R{L.key, (1u << lg) - 1u, ou, (MODE == WALK_ENUM_FILL) ? perm[u] : 0, 0};
     const double dmax_chunk = fabs(o_d[ou]);
     int64_t run_b = 0, run_u = 0;
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[it]; run_u = wp.off_u[it]; }
-    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE) {
-        int v, lv;
-        int64_t ov;
-        double duv;
-        int32_t euv;
-        CodeRow cr;
-        load_partners<MODE, shorter>(wp, o_off, o_adj, o_d, len, u, Lu, sb, np, i0, dmax_chunk,
-                                     v, ov, lv, duv, euv, cr);
-        // lane by lane (a loop over the set bits of a ballot made the sign-world walk 16%
-        // slower and the others no faster)
-        const int nv = min(UTRI_WAVE, np - i0);
-        for (int si = 0; si < nv; si++) {
-            const int lvs = bcast_i32(lv, si);
-            if (lvs == 0) continue;
-            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
-                               : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
-            const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
-                              (uint32_t)bcast_i32((int)cr.klo, si),
-                              bcast_i32(cr.neg_a ? 1 : 0, si) != 0};
-            stream_any<MODE>(wp, o_adj, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
-                             pv, crs, H, st, run_b, run_u);
-        }
-    }
+    walk_partners<MODE, shorter, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
+                                       0, 1, H, st, run_b, run_u);
     // an item counts at most its candidates per lane, far below 2^32
     st.nb += st.nb32;
     st.nu += st.nu32;
@@ -587,13 +784,14 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
 }
 
 // Work-group item: chunk `chunk` (CAPH entries) of a long source row, one shared table,
-// target rows split round-robin over the four waves. Enumeration slots are per wave.
-template <int MODE, bool shorter>
+// target rows split round-robin over the waves. Enumeration slots are per wave.
+template <int MODE, bool shorter, class G>
 __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                 const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
-                                const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                                int64_t item, int64_t hq, BlockLds& B, HistLds* H,
-                                WalkLaneState& st) {
+                                const int32_t* __restrict__ len, const uint2* __restrict__ rinfo,
+                                const int32_t* __restrict__ perm, int64_t item, int64_t hq,
+                                BlockTab<G>& B, HistLds* H, WalkLaneState& st) {
+    constexpr int WOFF = 4 << G::LGH;
     const int lane = utri_lane();
     const int wib = threadIdx.x / UTRI_WAVE;
     const int u = item_vertex(item);
@@ -606,40 +804,20 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     if (np <= 0) return;  // work-group uniform (the enumeration slots start zeroed)
     const int cb = chunk * CAPH;
     const int cl = min(CAPH, Lu - cb);
-    const int lg = table_lg(cl, SLOTSH);
-    const int nbk = 1 << lg;  // buckets
+    const int lg = tab_lg(cl, G::LGH);
     __syncthreads();  // the previous item's probes are done
-    for (int i = threadIdx.x; i < 4 * nbk; i += TPB) B.key[i] = 0;
+    tab_clear<WOFF>(B.key, lg, threadIdx.x, G::TPBW);
     __syncthreads();
-    stage_table(o_adj, ou + cb, cl, B.key, B.pos, lg, threadIdx.x, TPB, wp.idmask);
+    tab_stage<WOFF>(B.key, o_adj, o_d, ou + cb, cl, (1u << lg) - 1u, threadIdx.x, G::TPBW,
+                    wp.idmask);
     __syncthreads();
-    RowCtx R{B.key, B.pos, lg, (uint32_t)(nbk - 1), ou + cb,
-             (MODE == WALK_ENUM_FILL) ? perm[u] : 0, chunk};
+    const TabRef R{B.key, (1u << lg) - 1u, ou + cb, (MODE == WALK_ENUM_FILL) ? perm[u] : 0, chunk};
     const double dmax_chunk = fabs(o_d[ou + cb]);
-    const int64_t slot = wp.lb + 4 * hq + wib;
+    const int64_t slot = wp.lb + NW_MAX * hq + wib;
     int64_t run_b = 0, run_u = 0;
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[slot]; run_u = wp.off_u[slot]; }
-    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE) {
-        int v, lv;
-        int64_t ov;
-        double duv;
-        int32_t euv;
-        CodeRow cr;
-        load_partners<MODE, shorter>(wp, o_off, o_adj, o_d, len, u, Lu, sb, np, i0, dmax_chunk,
-                                     v, ov, lv, duv, euv, cr);
-        const int nv = min(UTRI_WAVE, np - i0);
-        for (int si = wib; si < nv; si += WPB) {
-            const int lvs = bcast_i32(lv, si);
-            if (lvs == 0) continue;
-            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
-                               : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
-            const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
-                              (uint32_t)bcast_i32((int)cr.klo, si),
-                              bcast_i32(cr.neg_a ? 1 : 0, si) != 0};
-            stream_any<MODE>(wp, o_adj, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
-                             pv, crs, H, st, run_b, run_u);
-        }
-    }
+    walk_partners<MODE, shorter, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
+                                       wib, G::NW, H, st, run_b, run_u);
     // an item counts at most its candidates per lane, far below 2^32
     st.nb += st.nb32;
     st.nu += st.nu32;
@@ -652,8 +830,7 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
 }
 
 template <int MODE>
-__device__ void walk_flush(const WalkParams& wp, const double* __restrict__ o_d, HistLds* H,
-                           WalkLaneState& st) {
+__device__ void walk_flush(const WalkParams& wp, HistLds* H, WalkLaneState& st) {
     const int lane = utri_lane();
     if (MODE == WALK_COUNT) {
         const uint64_t b = utri_wave_sum_u64(st.nb), u = utri_wave_sum_u64(st.nu);
@@ -696,17 +873,17 @@ __device__ void walk_flush(const WalkParams& wp, const double* __restrict__ o_d,
 }
 
 // Both phases of the walk for one work-group: heavy items cooperatively, then light
-// items one per wave. Heaviest rows (highest ids) go first in both lists.
-template <int MODE, bool shorter>
+// items one per wave. Heaviest rows (highest ids) go first in both lists; work queues:
+// qctr[0] hands out heavy items to work-groups, qctr[1] light items to waves in groups of
+// four.
+template <int MODE, bool shorter, class G>
 __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_off,
                             const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
-                            const int32_t* __restrict__ len, const int32_t* __restrict__ perm,
-                            const int64_t* __restrict__ items, int64_t nl, int64_t nh,
-                            WalkShared& S, HistLds* H, WalkLaneState& st) {
+                            const int32_t* __restrict__ len, const uint2* __restrict__ rinfo,
+                            const int32_t* __restrict__ perm, const int64_t* __restrict__ items,
+                            int64_t nl, int64_t nh, WalkShared<G>& S, HistLds* H,
+                            WalkLaneState& st) {
     const int wib = threadIdx.x / UTRI_WAVE;
-#if UTRI_WALK_DYNAMIC
-    // work queues: qctr[0] hands out heavy items to work-groups, qctr[1] light items to
-    // waves in groups of four
     __shared__ int64_t s_q;
     for (;;) {
         if (threadIdx.x == 0) s_q = (int64_t)atomicAdd(&wp.qctr[0], 1ull);
@@ -715,60 +892,38 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         __syncthreads();
         if (q >= nh) break;
         const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq,
-                                       S.block, H, st);
+        walk_item_block<MODE, shorter, G>(wp, o_off, o_adj, o_d, len, rinfo, perm,
+                                          items[wp.lb + hq], hq, S.block, H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
-#ifndef UTRI_WALK_QGROUP
-#define UTRI_WALK_QGROUP 4
-#endif
-#ifndef UTRI_WALK_QGROW
-#define UTRI_WALK_QGROW 0   // > 0: grab 1 + QGROW * (position / nl) items (lighter items later)
-#endif
-    int64_t last = 0;
+    constexpr int QGROUP = 4;
     for (;;) {
-        const int G = UTRI_WALK_QGROW > 0
-                          ? 1 + (int)((last * UTRI_WALK_QGROW) / (nl > 0 ? nl : 1))
-                          : UTRI_WALK_QGROUP;
         int64_t base = 0;
-        if (utri_lane() == 0) base = (int64_t)atomicAdd(&wp.qctr[1], (unsigned long long)G);
+        if (utri_lane() == 0) base = (int64_t)atomicAdd(&wp.qctr[1], (unsigned long long)QGROUP);
         base = bcast_i64(base, 0);
         if (base >= nl) break;
-        last = base;
-        const int64_t end = base + G < nl ? base + G : nl;
+        const int64_t end = base + QGROUP < nl ? base + QGROUP : nl;
         for (int64_t q = base; q < end; q++) {
             const int64_t it = nl - 1 - q;
-            walk_item_wave<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[it], it,
-                                          S.wave[wib], H, st);
+            walk_item_wave<MODE, shorter, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items[it],
+                                             it, S.wave[wib], H, st);
         }
     }
-#else
-    for (int64_t q = blockIdx.x; q < nh; q += gridDim.x) {
-        const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[wp.lb + hq], hq,
-                                       S.block, H, st);
-    }
-    __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wib;
-    const int64_t W = (int64_t)gridDim.x * WPB;
-    for (int64_t q = gw; q < nl; q += W) {
-        const int64_t it = nl - 1 - q;
-        walk_item_wave<MODE, shorter>(wp, o_off, o_adj, o_d, len, perm, items[it], it,
-                                      S.wave[wib], H, st);
-    }
-#endif
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __restrict__ o_off,
-                                              const int32_t* __restrict__ o_adj,
-                                              const double* __restrict__ o_d,
-                                              const int32_t* __restrict__ len,
-                                              const int32_t* __restrict__ perm,
-                                              const int64_t* __restrict__ items,
-                                              const int64_t* __restrict__ n_items_dev) {
-    __shared__ WalkShared S;
-    __shared__ HistLds hlds[MODE == WALK_HIST ? WPB : 1];
+__global__ void __launch_bounds__(GeomWalk::TPBW, UTRI_WALK_MIN_WAVES) k_walk(WalkParams wp,
+                                                          const int64_t* __restrict__ o_off,
+                                                          const int32_t* __restrict__ o_adj,
+                                                          const double* __restrict__ o_d,
+                                                          const int32_t* __restrict__ len,
+                                                          const uint2* __restrict__ rinfo,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int64_t* __restrict__ items,
+                                                          const int64_t* __restrict__ n_items_dev) {
+    using G = GeomWalk;
+    __shared__ WalkShared<G> S;
+    __shared__ HistLds hlds[MODE == WALK_HIST ? G::NW : 1];
     const int wib = threadIdx.x / UTRI_WAVE;
     HistLds* H = &hlds[MODE == WALK_HIST ? wib : 0];
     if (MODE == WALK_HIST) {
@@ -778,12 +933,12 @@ __global__ void __launch_bounds__(TPB) k_walk(WalkParams wp, const int64_t* __re
     WalkLaneState st;
     // both partner sources as their own code (the choice is uniform over the launch)
     if (stream_shorter<MODE>(wp, n_items_dev))
-        walk_phases<MODE, true>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                                n_items_dev[1], S, H, st);
+        walk_phases<MODE, true, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items, n_items_dev[0],
+                                   n_items_dev[1], S, H, st);
     else
-        walk_phases<MODE, false>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                                 n_items_dev[1], S, H, st);
-    walk_flush<MODE>(wp, o_d, H, st);
+        walk_phases<MODE, false, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items,
+                                    n_items_dev[0], n_items_dev[1], S, H, st);
+    walk_flush<MODE>(wp, H, st);
 }
 
 // Fused batch: the walk (threshold histogram of every triangle at the smallest
@@ -793,14 +948,17 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
                                                const int32_t* __restrict__ o_adj,
                                                const double* __restrict__ o_d,
                                                const int32_t* __restrict__ len,
+                                               const uint2* __restrict__ rinfo,
                                                const int32_t* __restrict__ perm,
                                                const int64_t* __restrict__ items,
                                                const int64_t* __restrict__ n_items_dev,
-                                               SampleParams sp, SampleGraph G,
+                                               SampleParams sp, SampleGraph SG,
                                                const int32_t* __restrict__ slen) {
+    using G = GeomBatch;
+    static_assert(G::TPBW == TPB, "the batch shares the sampler's block size");
     // the walk's tables and the sampler's tables are used one after the other
     union BatchLds {
-        WalkShared walk;
+        WalkShared<G> walk;
         SampleLds samp;
     };
     __shared__ BatchLds S;
@@ -814,15 +972,15 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
     WalkLaneState st;
     if (wp.acc != nullptr) {
         if (stream_shorter<WALK_HIST>(wp, n_items_dev))
-            walk_phases<WALK_HIST, true>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                                         n_items_dev[1], S.walk, H, st);
+            walk_phases<WALK_HIST, true, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items,
+                                            n_items_dev[0], n_items_dev[1], S.walk, H, st);
         else
-            walk_phases<WALK_HIST, false>(wp, o_off, o_adj, o_d, len, perm, items, n_items_dev[0],
-                                          n_items_dev[1], S.walk, H, st);
-        walk_flush<WALK_HIST>(wp, o_d, H, st);
+            walk_phases<WALK_HIST, false, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items,
+                                             n_items_dev[0], n_items_dev[1], S.walk, H, st);
+        walk_flush<WALK_HIST>(wp, H, st);
     }
     __syncthreads();  // the walk's tables are no longer read; the sampler's reuse them
-    if (sp.hist != nullptr && sp.t1 > sp.t0) sample_groups(sp, G, slen, S.samp);
+    if (sp.hist != nullptr && sp.t1 > sp.t0) sample_groups(sp, SG, slen, S.samp);
 }
 
 }  // namespace
@@ -832,7 +990,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     (void)cap;
     const int64_t n = g->n;
     const int64_t lb = light_bound(g), hb = heavy_bound(g);
-    void *plen, *pcnt, *poff, *pitems, *pn;
+    void *plen, *pcnt, *poff, *pitems, *pn, *pri;
     // oriented prefixes in [0, n], symmetric prefixes in [n + 1, 2n + 1]
     UTRI_TRY(utri_scratch(g, SCR_LEN, sizeof(int32_t) * (size_t)(2 * n + 2), &plen));
     UTRI_TRY(utri_scratch(g, SCR_ICNT, sizeof(int32_t) * (size_t)(2 * n + 2), &pcnt));
@@ -841,9 +999,12 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     // [0] light items, [1] heavy items, [2..3] work-queue counters, then the slot pairs of
     // the kept oriented edges and of the ids the plain forward iteration would stream
     UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * NITEMS_WORDS, &pn));
+    // per vertex: (row start, kept length) for the partner scans
+    UTRI_TRY(utri_scratch(g, SCR_RINFO, sizeof(uint2) * (size_t)std::max<int64_t>(n, 1), &pri));
     *items = (int64_t*)pitems;
     *n_items_dev = (int64_t*)pn;
     *len = (int32_t*)plen;
+    g->rinfo_cur = pri;
     UTRI_TRY(utri_fill_u64(pn, 0, NITEMS_WORDS, s));
     if (n == 0) return UTRI_OK;
     int32_t* lcnt = (int32_t*)pcnt;
@@ -854,7 +1015,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     int32_t* slen = (int32_t*)plen + n + 1;
     hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, g->s_off,
                        g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt,
-                       (unsigned long long*)pn + 4);
+                       (unsigned long long*)pn + 4, (uint2*)pri);
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
     UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
@@ -866,7 +1027,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
 }
 
 // Graph-dependent fields of a launch: enumeration slot base, row packing, symmetric rows
-// and their kept prefixes (stored after the oriented ones), FP32 bounds of c.
+// and their kept prefixes (stored after the oriented ones).
 static void set_launch_fields(utri_graph* g, WalkParams& wp, const int32_t* len) {
     wp.lb = light_bound(g);
     wp.order = g->walk_order;
@@ -875,14 +1036,10 @@ static void set_launch_fields(utri_graph* g, WalkParams& wp, const int32_t* len)
     wp.s_d = g->s_d;
     wp.s_eid = g->s_eid;
     wp.slen = len ? len + g->n + 1 : nullptr;
+    wp.o_adj = g->o_adj;
     wp.idmask = g->idmask;
     wp.idbits = g->idbits;
     wp.mb = g->code_mb;
-    float up = (float)wp.c, dn = (float)wp.c;
-    if ((double)up < wp.c) up = nextafterf(up, INFINITY);
-    if ((double)dn > wp.c) dn = nextafterf(dn, -INFINITY);
-    wp.c_up = up;
-    wp.c_dn = dn;
 }
 
 int64_t utri_count_scratch_bound(const utri_graph* g, int64_t align) {
@@ -894,6 +1051,7 @@ int64_t utri_count_scratch_bound(const utri_graph* g, int64_t align) {
         8 * (2 * n + 2),                          // their offsets
         8 * (light_bound(g) + heavy_bound(g)),    // work items
         8 * (int64_t)NITEMS_WORDS,                // item counts, queues, kept totals
+        8 * std::max<int64_t>(n, 1),              // row starts and kept lengths
         8 * scan_blocks,                          // scan partials
         8 * 4,                                    // class counters
     };
@@ -902,26 +1060,27 @@ int64_t utri_count_scratch_bound(const utri_graph* g, int64_t align) {
     return tot;
 }
 
-// Slots of the per-item enumeration arrays: one per light item, four per heavy item.
-int64_t utri_walk_items_bound(utri_graph* g) { return light_bound(g) + 4 * heavy_bound(g); }
+// Slots of the per-item enumeration arrays: one per light item, NW_MAX per heavy item.
+int64_t utri_walk_items_bound(utri_graph* g) { return light_bound(g) + NW_MAX * heavy_bound(g); }
 
 // Work-groups per CU for a kernel: the resident occupancy (so no second, partial round of
-// work-groups trails the statically strided items), unless a tuned value is set.
+// work-groups trails the items), unless a tuned value is set.
 template <class K>
-static int blocks_per_cu(utri_graph* g, K kernel) {
+static int blocks_per_cu(utri_graph* g, K kernel, int tpb) {
     if (g->walk_blocks_per_cu > 0) return g->walk_blocks_per_cu;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, TPB, 0) != hipSuccess || nb < 1)
-        nb = 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, tpb, 0) != hipSuccess || nb < 1)
+        nb = 2;
     return nb;
 }
 
 template <int MODE>
 static void launch_walk(utri_graph* g, const WalkParams& wp, const int32_t* len,
                         const int64_t* items, const int64_t* n_items_dev, hipStream_t s) {
-    const int blocks = g->num_cu * blocks_per_cu(g, k_walk<MODE>);
-    hipLaunchKernelGGL(k_walk<MODE>, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj,
-                       g->o_d, len, g->perm, items, n_items_dev);
+    const int tpb = GeomWalk::TPBW;
+    const int blocks = g->num_cu * blocks_per_cu(g, k_walk<MODE>, tpb);
+    hipLaunchKernelGGL(k_walk<MODE>, dim3(blocks), dim3(tpb), 0, s, wp, g->o_off, g->o_adj,
+                       g->o_d, len, (const uint2*)g->rinfo_cur, g->perm, items, n_items_dev);
 }
 
 int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int64_t* items,
@@ -959,9 +1118,9 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
                   g->h_key, g->h_d};
-    const int blocks = g->num_cu * blocks_per_cu(g, k_batch);
+    const int blocks = g->num_cu * blocks_per_cu(g, k_batch, TPB);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj, g->o_d,
-                       len, g->perm, items, n_items_dev, sp, G, slen);
+                       len, (const uint2*)g->rinfo_cur, g->perm, items, n_items_dev, sp, G, slen);
     UTRI_HIP_TRY(hipGetLastError());
     return UTRI_OK;
 }
