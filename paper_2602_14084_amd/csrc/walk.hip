@@ -333,7 +333,7 @@ constexpr int SIGN_Q = 128;  // triangles queued per wave
 
 struct WalkLaneState {
     uint64_t nb = 0, nu = 0;       // COUNT / ENUM_COUNT
-    uint32_t nb32 = 0, nu32 = 0;   // COUNT / ENUM_COUNT within one item (added to nb / nu)
+    uint32_t nb32 = 0, nu32 = 0;   // COUNT / ENUM_COUNT within one item: balanced, classified
     uint64_t tri = 0;              // EXPECTED / STATS
     uint64_t slo = 0;              // EXPECTED: sum of low 32 bits of each fixed-point term
     int64_t shi = 0;               // EXPECTED: sum of the terms shifted right by 32
@@ -456,7 +456,7 @@ __device__ __forceinline__ void defer_drain(const WalkParams& wp, const double* 
         if (live) {
             const double s = utri_tri_s(duv, o_d[src_base + (ps & W_POS)], o_d[vw]);
             st.nb32 += (s <= -wp.c) ? 1u : 0u;
-            st.nu32 += (s > wp.c) ? 1u : 0u;
+            st.nu32 += (s <= -wp.c || s > wp.c) ? 1u : 0u;
         }
     }
     st.dn = 0;
@@ -512,7 +512,37 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
             const uint32_t w = pw[k] & wp.idmask;
             const uint32_t r = tab_find<WOFF>(R.key, R.bmask, w);
             const bool found = r != 0u;
-            if (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT || MODE == WALK_ENUM_FILL) {
+            if (kDefer) {
+                // classified hits are counted as (classified, of which s < 0: balanced); the
+                // undecided ones are queued for the exact rule
+                const uint32_t qb = __builtin_amdgcn_ubfe(r, 16, QB);
+                const uint32_t qc = __builtin_amdgcn_ubfe(pw[k], wp.idbits, wp.mb);
+                const uint32_t p0 = __umul24(qb, qc);
+                const uint32_t t1 = p0 + qb + qc;  // (qb + 1)(qc + 1) - 1
+                const bool ccls = p0 >= cr.khi;
+                const uint32_t cls = (found && ccls) ? 1u : 0u;
+                st.nb32 += cls & ((r ^ pw[k] ^ cr.rsign) >> 31);
+                st.nu32 += cls;
+                const bool und = found && !ccls && t1 >= cr.klo;
+                const uint64_t um = __ballot(und);
+                if (um) {
+                    const int nq = __popcll(um);
+                    if (st.dn + nq <= DQ_CAP) {
+                        if (und) {
+                            DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+                            const int slot = st.dn + __popcll(um & __lanemask_lt());
+                            Q.vw[slot] = (uint32_t)(ovs + j);
+                            Q.ps[slot] = (r & W_POS) | ((uint32_t)si << 15);
+                        }
+                        st.dn += nq;
+                    } else if (und) {
+                        const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
+                        const uint32_t c = (s <= -wp.c || s > wp.c) ? 1u : 0u;
+                        st.nb32 += (s <= -wp.c) ? 1u : 0u;
+                        st.nu32 += c;
+                    }
+                }
+            } else if (MODE == WALK_ENUM_FILL) {
                 bool is_b = false, is_u = false;
                 bool und = found;
                 if (kCoded) {
@@ -527,27 +557,7 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
                     is_u = found && cls && !neg;
                     und = found && !cls && !nei;
                 }
-                if (kDefer) {
-                    st.nb32 += is_b ? 1u : 0u;
-                    st.nu32 += is_u ? 1u : 0u;
-                    const uint64_t um = __ballot(und);
-                    if (um) {
-                        const int nq = __popcll(um);
-                        if (st.dn + nq <= DQ_CAP) {
-                            if (und) {
-                                DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
-                                const int slot = st.dn + __popcll(um & __lanemask_lt());
-                                Q.vw[slot] = (uint32_t)(ovs + j);
-                                Q.ps[slot] = (r & W_POS) | ((uint32_t)si << 15);
-                            }
-                            st.dn += nq;
-                        } else if (und) {
-                            const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
-                            st.nb32 += (s <= -wp.c) ? 1u : 0u;
-                            st.nu32 += (s > wp.c) ? 1u : 0u;
-                        }
-                    }
-                } else {
+                {
                     if (und) {
                         // the exact FP64 rule reads d_uw and d_vw
                         const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
@@ -656,18 +666,18 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const double* _
                                   run_b, run_u);
 }
 
-// Load, on lane i, partner y = entry sb + i0 + i of the kept symmetric row of x (np
-// entries in this item's range) with the start of N+(y), the kept length of N+(y) this
-// item streams (0 when the edge {x, y} is streamed from y's side, see k_items), d_xy and
-// the edge id (sign worlds).
+// Load, on lane l, partner y = entry sb + i0 + l * nparts + part of the kept symmetric row
+// of x (np entries in this item's range; the waves of a work-group take every nparts-th
+// partner) with the start of N+(y), the kept length of N+(y) this item streams (0 when the
+// edge {x, y} is streamed from y's side, see k_items), d_xy and the edge id (sign worlds).
 template <int MODE, bool shorter>
 __device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
                                               const uint2* __restrict__ rinfo, int x, int Lx,
-                                              int64_t sb, int np, int i0, double dmax_chunk,
-                                              int& y, int64_t& oy, int& ly, double& dxy,
-                                              int32_t& exy, CodeRow& cr) {
-    const int i = i0 + utri_lane();
+                                              int64_t sb, int np, int i0, int part, int nparts,
+                                              double dmax_chunk, int& y, int64_t& oy, int& ly,
+                                              double& dxy, int32_t& exy, CodeRow& cr) {
+    const int i = i0 + utri_lane() * nparts + part;
     ly = 0; y = 0; oy = 0; dxy = 0.0; exy = 0;
     cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.rsign = 0u;
     if (i < np) {
@@ -704,7 +714,8 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_
 #endif
 
 // Stream every partner row of one partner range of an item through the staged table;
-// partner si of a batch of 64 goes to the wave with si % nparts == part.
+// partner p goes to the wave with p % nparts == part, which loads its own partners 64 at a
+// time.
 template <int MODE, bool shorter, int WOFF>
 __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
@@ -713,18 +724,19 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
                                               int u, int Lu, int64_t sb, int np, double dmax_chunk,
                                               int part, int nparts, HistLds* H, WalkLaneState& st,
                                               int64_t& run_b, int64_t& run_u) {
-    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE) {
+    for (int i0 = 0; i0 < np; i0 += UTRI_WAVE * nparts) {
         int v, lv;
         int64_t ov;
         double duv;
         int32_t euv;
         CodeRow cr;
-        load_partners<MODE, shorter>(wp, o_adj, o_d, rinfo, u, Lu, sb, np, i0, dmax_chunk, v, ov,
-                                     lv, duv, euv, cr);
-        const int nv = min(UTRI_WAVE, np - i0);
+        load_partners<MODE, shorter>(wp, o_adj, o_d, rinfo, u, Lu, sb, np, i0, part, nparts,
+                                     dmax_chunk, v, ov, lv, duv, euv, cr);
+        // this wave's partners in the batch: i0 + part + nparts * si < np
+        const int nv = min(UTRI_WAVE, (np - i0 - part + nparts - 1) / nparts);
         // lane by lane (a loop over the set bits of a ballot made the sign-world walk slower
         // and the others no faster)
-        for (int si = part; si < nv; si += nparts) {
+        for (int si = 0; si < nv; si++) {
             const int lvs = bcast_i32(lv, si);
             if (lvs == 0) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
@@ -771,9 +783,10 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[it]; run_u = wp.off_u[it]; }
     walk_partners<MODE, shorter, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
                                        0, 1, H, st, run_b, run_u);
-    // an item counts at most its candidates per lane, far below 2^32
+    // an item counts at most its candidates per lane, far below 2^32; the counting walks
+    // keep (balanced, classified) per lane
     st.nb += st.nb32;
-    st.nu += st.nu32;
+    st.nu += (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) ? st.nu32 - st.nb32 : st.nu32;
     st.nb32 = st.nu32 = 0;
     if (MODE == WALK_ENUM_COUNT) {
         const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
@@ -818,9 +831,10 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[slot]; run_u = wp.off_u[slot]; }
     walk_partners<MODE, shorter, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
                                        wib, G::NW, H, st, run_b, run_u);
-    // an item counts at most its candidates per lane, far below 2^32
+    // an item counts at most its candidates per lane, far below 2^32; the counting walks
+    // keep (balanced, classified) per lane
     st.nb += st.nb32;
-    st.nu += st.nu32;
+    st.nu += (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) ? st.nu32 - st.nb32 : st.nu32;
     st.nb32 = st.nu32 = 0;
     if (MODE == WALK_ENUM_COUNT) {
         const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
