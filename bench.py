@@ -313,6 +313,7 @@ def cpu_detail(inputs):
             t = time.time()
             og2.count(tau)
             r[f"rmat_s20_beta22_count_t{tau}_s"] = time.time() - t
+            log(f"cpu detail: s20 count at t={tau} on {th} threads {time.time() - t:.1f}s")
         out[f"threads_{th}"] = r
         log(f"cpu detail on {th} threads: {r}")
     oracle.set_threads(all_threads)

@@ -248,10 +248,51 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
                int64_t* exact, double* est, int use_graph, void* hip_stream);
 
 /*
- * Launch-shape autotuner: times the walk and sampler kernels on this graph over a small
- * grid of work-group counts and sample-chunk sizes and keeps the fastest for later
- * calls. If cache_path is not NULL the choice is stored there as one JSON line keyed by
- * (n, m, max degree) and reused by later handles of the same shape.
+ * Launch parameters of the walk and the sampler (the work-chunk and tile sizes of the
+ * kernels that run Sections 4-6; no value changes any result), as int64 in this order:
+ *   UTRI_TUNE_WALK_BLOCKS_PER_CU  walk work-groups per compute unit, 0 = the kernel's
+ *                                 resident occupancy (default 0; 0..64);
+ *   UTRI_TUNE_SAMPLE_CHUNK        draws per sampler group item (default 128; a multiple
+ *                                 of 64 in 64..4096);
+ *   UTRI_TUNE_WALK_PARTNERS       neighbours (partner rows) per walk work item (default
+ *                                 1024; a multiple of 64 in 64..2^20);
+ *   UTRI_TUNE_WALK_LIGHT_CAP      longest kept row staged by one wavefront, longer rows
+ *                                 go to work-groups (default 128; a power of two, 8..128);
+ *   UTRI_TUNE_WALK_CHUNK          row entries per work-group table chunk (default 2048; a
+ *                                 power of two, at least 256 and the light cap, at most
+ *                                 2048);
+ *   UTRI_TUNE_WALK_UNROLL         row loads in flight per lane (default 8; 1, 2, 4, 8);
+ *   UTRI_TUNE_WALK_SHORTER_MIN    under UTRI_ORDER_AUTO the walk streams the shorter kept
+ *                                 row of each edge when the plain forward iteration would
+ *                                 stream at least this many ids per kept edge (default
+ *                                 320; 0..2^40).
+ * utri_get_tuning writes the handle's current values to out (host int64
+ * [UTRI_TUNE_COUNT]); utri_set_tuning validates all of in (host) and applies them to later
+ * calls on g, or changes nothing and returns UTRI_E_INVALID.
+ */
+enum {
+    UTRI_TUNE_WALK_BLOCKS_PER_CU = 0,
+    UTRI_TUNE_SAMPLE_CHUNK = 1,
+    UTRI_TUNE_WALK_PARTNERS = 2,
+    UTRI_TUNE_WALK_LIGHT_CAP = 3,
+    UTRI_TUNE_WALK_CHUNK = 4,
+    UTRI_TUNE_WALK_UNROLL = 5,
+    UTRI_TUNE_WALK_SHORTER_MIN = 6,
+    UTRI_TUNE_COUNT = 7
+};
+int utri_get_tuning(utri_graph* g, int64_t out[UTRI_TUNE_COUNT]);
+int utri_set_tuning(utri_graph* g, const int64_t in[UTRI_TUNE_COUNT]);
+
+/*
+ * Autotuner: picks the launch parameters above for this graph by timing the pruned
+ * count at t (coordinate descent: work-groups per CU, partners per item, chunk size,
+ * light cap, loads in flight, each over a few values, then the shorter-row crossover
+ * moved so that t's query takes the faster of the two row orders) and the sampler at t
+ * (draws per group item), and keeps the fastest for later calls on g. If cache_path is
+ * not NULL and the file holds a choice for this graph shape (n, m, max degree), that
+ * choice is applied without timing; otherwise the new choice is appended to it as one
+ * JSON line. Handles created while the environment variable UTRI_TUNE_CACHE names such a
+ * file start from its choice. Results never depend on these parameters.
  */
 int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream);
 

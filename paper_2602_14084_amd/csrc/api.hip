@@ -242,20 +242,66 @@ std::string cache_key(const utri_graph* g) {
     return buf;
 }
 
-void apply_cache(utri_graph* g, const char* path) {
-    if (!path) return;
+// The launch parameters in UTRI_TUNE_* order, and their JSON names in the cache file.
+const char* const TUNE_NAMES[UTRI_TUNE_COUNT] = {
+    "walk_blocks_per_cu", "sample_chunk", "walk_partners", "walk_light_cap",
+    "walk_chunk",         "walk_unroll",  "walk_shorter_min"};
+
+void tune_get(const utri_graph* g, int64_t v[UTRI_TUNE_COUNT]) {
+    v[UTRI_TUNE_WALK_BLOCKS_PER_CU] = g->walk_blocks_per_cu;
+    v[UTRI_TUNE_SAMPLE_CHUNK] = g->sample_chunk;
+    v[UTRI_TUNE_WALK_PARTNERS] = g->walk_tune.pr;
+    v[UTRI_TUNE_WALK_LIGHT_CAP] = g->walk_tune.cap;
+    v[UTRI_TUNE_WALK_CHUNK] = g->walk_tune.caph;
+    v[UTRI_TUNE_WALK_UNROLL] = g->walk_tune.unr;
+    v[UTRI_TUNE_WALK_SHORTER_MIN] = g->walk_tune.shorter_min;
+}
+
+int tune_set(utri_graph* g, const int64_t v[UTRI_TUNE_COUNT]) {
+    const int64_t b = v[UTRI_TUNE_WALK_BLOCKS_PER_CU], c = v[UTRI_TUNE_SAMPLE_CHUNK];
+    if (b < 0 || b > 64 || c < 64 || c > 4096 || c % 64 != 0) return UTRI_E_INVALID;
+    for (int i = UTRI_TUNE_WALK_PARTNERS; i <= UTRI_TUNE_WALK_UNROLL; i++)
+        if (v[i] < 0 || v[i] > (1 << 20)) return UTRI_E_INVALID;
+    WalkTune t;
+    t.pr = (int32_t)v[UTRI_TUNE_WALK_PARTNERS];
+    t.cap = (int32_t)v[UTRI_TUNE_WALK_LIGHT_CAP];
+    t.caph = (int32_t)v[UTRI_TUNE_WALK_CHUNK];
+    t.unr = (int32_t)v[UTRI_TUNE_WALK_UNROLL];
+    t.shorter_min = v[UTRI_TUNE_WALK_SHORTER_MIN];
+    if (!utri_walk_tune_ok(t)) return UTRI_E_INVALID;
+    g->walk_blocks_per_cu = (int)b;
+    g->sample_chunk = (int)c;
+    g->walk_tune = t;
+    return UTRI_OK;
+}
+
+// The cached choice for g's shape in the file at path (the last matching line wins);
+// false if there is none or it does not validate.
+bool read_cache(const utri_graph* g, const char* path, int64_t v[UTRI_TUNE_COUNT]) {
+    if (!path) return false;
     FILE* f = fopen(path, "r");
-    if (!f) return;
-    char line[512];
+    if (!f) return false;
+    char line[1024];
     const std::string key = cache_key(g);
+    bool found = false;
     while (fgets(line, sizeof(line), f)) {
         if (!strstr(line, key.c_str())) continue;
-        const char* a = strstr(line, "\"walk_blocks_per_cu\": ");
-        const char* b = strstr(line, "\"sample_chunk\": ");
-        if (a) g->walk_blocks_per_cu = std::max(0, atoi(a + 22));
-        if (b) g->sample_chunk = std::max(64, atoi(b + 16) / 64 * 64);
+        int64_t w[UTRI_TUNE_COUNT];
+        tune_get(g, w);
+        for (int i = 0; i < UTRI_TUNE_COUNT; i++) {
+            const std::string name = std::string("\"") + TUNE_NAMES[i] + "\": ";
+            if (const char* a = strstr(line, name.c_str())) w[i] = atoll(a + name.size());
+        }
+        for (int i = 0; i < UTRI_TUNE_COUNT; i++) v[i] = w[i];
+        found = true;
     }
     fclose(f);
+    return found;
+}
+
+void apply_cache(utri_graph* g, const char* path) {
+    int64_t v[UTRI_TUNE_COUNT];
+    if (read_cache(g, path, v)) (void)tune_set(g, v);  // an invalid line keeps the defaults
 }
 
 // ------------------------------------------------------------------ no-allocation counting
@@ -781,7 +827,7 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
                       B.est == est && B.cvals == cv && B.scr_gen == g->scr_gen &&
                       B.walk_blocks_per_cu == g->walk_blocks_per_cu &&
                       B.sample_chunk == g->sample_chunk && B.sample_pass == g->sample_pass &&
-                      B.walk_order == g->walk_order;
+                      B.walk_order == g->walk_order && B.walk_tune == g->walk_tune;
     if (!same) {
         if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
         if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
@@ -810,6 +856,7 @@ int utri_batch(utri_graph* g, const double* t, int nt, int64_t k, int32_t worlds
         B.sample_chunk = g->sample_chunk;
         B.sample_pass = g->sample_pass;
         B.walk_order = g->walk_order;
+        B.walk_tune = g->walk_tune;
     }
     // thresholds and seed are read from device buffers written above on `s`
     UTRI_HIP_TRY(hipGraphLaunch(B.exec, gs));
@@ -877,9 +924,27 @@ int utri_set_walk_order(utri_graph* g, int order) {
     return UTRI_OK;
 }
 
+int utri_get_tuning(utri_graph* g, int64_t out[UTRI_TUNE_COUNT]) {
+    UTRI_TRY(check_graph(g));
+    if (!out) return UTRI_E_INVALID;
+    tune_get(g, out);
+    return UTRI_OK;
+}
+
+int utri_set_tuning(utri_graph* g, const int64_t in[UTRI_TUNE_COUNT]) {
+    UTRI_TRY(check_graph(g));
+    if (!in) return UTRI_E_INVALID;
+    return tune_set(g, in);
+}
+
 int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_stream) {
     UTRI_TRY(check_graph(g));
     if (!t_ok(t)) return UTRI_E_INVALID;
+    // a choice cached for this graph shape is taken as it is
+    {
+        int64_t v[UTRI_TUNE_COUNT];
+        if (read_cache(g, cache_path, v) && tune_set(g, v) == UTRI_OK) return UTRI_OK;
+    }
     hipStream_t s = as_stream(hip_stream);
     // events are released on every return path
     struct Events {
@@ -891,27 +956,75 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
     } ev;
     UTRI_HIP_TRY(hipEventCreate(&ev.a));
     UTRI_HIP_TRY(hipEventCreate(&ev.b));
-    hipEvent_t e0 = ev.a, e1 = ev.b;
-    int64_t out[2];
-    float best = 1e30f;
-    int best_b = g->walk_blocks_per_cu;
-    // 0 = the kernel's resident occupancy; multiples of it trade tail balance for overhead
-    for (int b : {0, 3, 12, 18}) {
-        g->walk_blocks_per_cu = b;
-        UTRI_TRY(count_impl(g, t, UTRI_PRUNED, out, s));  // warm-up
+    // the counting query at t: one warm-up, then the summed time of three runs
+    const auto time_count = [&](float* ms_out) -> int {
+        int64_t out[2];
+        UTRI_TRY(count_impl(g, t, UTRI_PRUNED, out, s));
         float tot = 0.f;
         for (int r = 0; r < 3; r++) {
-            UTRI_HIP_TRY(hipEventRecord(e0, s));
+            UTRI_HIP_TRY(hipEventRecord(ev.a, s));
             UTRI_TRY(count_impl(g, t, UTRI_PRUNED, out, s));
-            UTRI_HIP_TRY(hipEventRecord(e1, s));
-            UTRI_HIP_TRY(hipEventSynchronize(e1));
+            UTRI_HIP_TRY(hipEventRecord(ev.b, s));
+            UTRI_HIP_TRY(hipEventSynchronize(ev.b));
             float ms = 0.f;
-            UTRI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            UTRI_HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
             tot += ms;
         }
-        if (tot < best) { best = tot; best_b = b; }
+        *ms_out = tot;
+        return UTRI_OK;
+    };
+    // coordinate descent over the walk's launch parameters, one at a time in this order,
+    // each kept at its fastest value for the rest
+    int64_t cur[UTRI_TUNE_COUNT];
+    tune_get(g, cur);
+    struct Axis {
+        int idx;
+        std::vector<int64_t> vals;
+    };
+    // 0 work-groups per CU = the kernel's resident occupancy; more trade tail balance for
+    // overhead
+    const Axis axes[] = {
+        {UTRI_TUNE_WALK_BLOCKS_PER_CU, {0, 2, 3, 8}},
+        {UTRI_TUNE_WALK_PARTNERS, {256, 512, 1024, 2048, 4096}},
+        {UTRI_TUNE_WALK_CHUNK, {512, 1024, 2048}},
+        {UTRI_TUNE_WALK_LIGHT_CAP, {32, 64, 128}},
+        {UTRI_TUNE_WALK_UNROLL, {2, 4, 8}},
+    };
+    for (const Axis& ax : axes) {
+        float best = 1e30f;
+        int64_t best_v = cur[ax.idx];
+        for (int64_t v : ax.vals) {
+            int64_t trial[UTRI_TUNE_COUNT];
+            for (int i = 0; i < UTRI_TUNE_COUNT; i++) trial[i] = cur[i];
+            trial[ax.idx] = v;
+            if (tune_set(g, trial) != UTRI_OK) continue;  // e.g. a chunk below the light cap
+            float ms = 0.f;
+            UTRI_TRY(time_count(&ms));
+            if (ms < best) { best = ms; best_v = v; }
+        }
+        cur[ax.idx] = best_v;
+        UTRI_TRY(tune_set(g, cur));
     }
-    g->walk_blocks_per_cu = best_b;
+    // the shorter-row crossover: time both orders at t and move the crossover so that this
+    // query's ratio (ids the plain order streams per kept edge) takes the faster one
+    if (g->walk_order == UTRI_ORDER_AUTO) {
+        float ms_short = 0.f, ms_plain = 0.f;
+        int64_t trial[UTRI_TUNE_COUNT];
+        for (int i = 0; i < UTRI_TUNE_COUNT; i++) trial[i] = cur[i];
+        trial[UTRI_TUNE_WALK_SHORTER_MIN] = 0;  // always the shorter row
+        UTRI_TRY(tune_set(g, trial));
+        UTRI_TRY(time_count(&ms_short));
+        double ratio = 0.0;
+        UTRI_TRY(utri_walk_plain_ratio(g, s, &ratio));
+        trial[UTRI_TUNE_WALK_SHORTER_MIN] = (int64_t)1 << 40;  // never
+        UTRI_TRY(tune_set(g, trial));
+        UTRI_TRY(time_count(&ms_plain));
+        const int64_t def = WalkTune{}.shorter_min;
+        const int64_t r = (int64_t)std::min(ratio, 1e12);
+        cur[UTRI_TUNE_WALK_SHORTER_MIN] =
+            ms_short < ms_plain ? std::min<int64_t>(def, r) : std::max<int64_t>(def, r + 1);
+        UTRI_TRY(tune_set(g, cur));
+    }
     // draws per sampler group item
     std::vector<double> tv{t};
     const int32_t worlds = 64;
@@ -927,13 +1040,13 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
         if (rc != UTRI_OK) return rc;
         float tot = 0.f;
         for (int r = 0; r < 3; r++) {
-            UTRI_HIP_TRY(hipEventRecord(e0, s));
+            UTRI_HIP_TRY(hipEventRecord(ev.a, s));
             rc = utri_sample(g, tv.data(), 1, k, worlds, 12345, UTRI_SAMPLE_EDGE, est, hip_stream);
-            UTRI_HIP_TRY(hipEventRecord(e1, s));
-            UTRI_HIP_TRY(hipEventSynchronize(e1));
+            UTRI_HIP_TRY(hipEventRecord(ev.b, s));
+            UTRI_HIP_TRY(hipEventSynchronize(ev.b));
             if (rc != UTRI_OK) return rc;
             float ms = 0.f;
-            UTRI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            UTRI_HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
             tot += ms;
         }
         if (tot < best_s) { best_s = tot; best_c = c; }
@@ -942,8 +1055,13 @@ int utri_autotune(utri_graph* g, double t, const char* cache_path, void* hip_str
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "{%s, \"walk_blocks_per_cu\": %d, \"sample_chunk\": %d}\n",
-                    cache_key(g).c_str(), g->walk_blocks_per_cu, g->sample_chunk);
+            int64_t v[UTRI_TUNE_COUNT];
+            tune_get(g, v);
+            std::string line = "{" + cache_key(g);
+            for (int i = 0; i < UTRI_TUNE_COUNT; i++)
+                line += std::string(", \"") + TUNE_NAMES[i] + "\": " + std::to_string(v[i]);
+            line += "}\n";
+            fputs(line.c_str(), f);
             fclose(f);
         }
     }

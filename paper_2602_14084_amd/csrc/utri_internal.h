@@ -123,6 +123,27 @@ enum UtriScratch {
     SCR_COUNT
 };
 
+// Run-time launch parameters of the triangle walk (the autotuner's search space; every
+// value gives the same results):
+//   pr    partners (symmetric-row entries) per work item, a multiple of 64;
+//   cap   longest kept row staged in one wave's table (longer rows go to work-groups),
+//         a power of two <= 128;
+//   caph  entries per work-group table chunk, a power of two in [cap, 2048];
+//   unr   most row loads in flight per lane (1, 2, 4 or 8);
+//   shorter_min  the walk streams the shorter kept row of each edge when the plain
+//         forward iteration would stream at least this many ids per kept edge.
+struct WalkTune {
+    int32_t pr = 1024;
+    int32_t cap = 128;
+    int32_t caph = 2048;
+    int32_t unr = 8;
+    int64_t shorter_min = 320;
+    bool operator==(const WalkTune& o) const {
+        return pr == o.pr && cap == o.cap && caph == o.caph && unr == o.unr &&
+               shorter_min == o.shorter_min;
+    }
+};
+
 struct UtriBatchGraph {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -139,6 +160,7 @@ struct UtriBatchGraph {
     uint64_t scr_gen = 0;
     int walk_blocks_per_cu = 0, sample_chunk = 0, walk_order = 0;
     int64_t sample_pass = 0;
+    WalkTune walk_tune;
 };
 
 struct utri_graph {
@@ -196,6 +218,7 @@ struct utri_graph {
     int64_t sample_pass = UTRI_SAMPLE_PASS;  // draws grouped per sampler pass
     uint32_t sign_flush_at = 65535;          // sign-world counter additions between flushes
     int walk_order = 0;                      // UTRI_ORDER_*: row streamed per kept edge
+    WalkTune walk_tune;                      // walk work-chunk and tile sizes
 
     // gradient: item counts of its four lists and partial-slice totals (they depend on the
     // degrees only), -1 = not read yet
@@ -427,6 +450,7 @@ struct WalkParams {
     const int32_t* s_eid = nullptr;
     const int32_t* slen = nullptr;
     int order = 0;                      // UTRI_ORDER_* (set at launch)
+    WalkTune tune;                      // work-chunk and tile sizes (set at launch)
     const int32_t* o_adj = nullptr;     // packed oriented rows (set at launch)
 };
 
@@ -487,6 +511,10 @@ int utri_finalize_launch(const unsigned long long* hist, int rows, int nt, const
 int utri_edge_local_launch(utri_graph* g, const double* cvals, const int32_t* order, int nt,
                            const int64_t* eids, int64_t k, int64_t* out, hipStream_t s);
 int64_t utri_walk_items_bound(utri_graph* g);
+// Whether run-time walk launch parameters fit the compiled table geometry.
+bool utri_walk_tune_ok(const WalkTune& t);
+// Ids the plain forward iteration streams per kept edge at the last prepared query.
+int utri_walk_plain_ratio(utri_graph* g, hipStream_t s, double* ratio);
 // Upper bound of the scratch bytes one counting query requests (row prefixes, work items,
 // counters, scan partials, accumulators), with `align` bytes of padding per buffer.
 int64_t utri_count_scratch_bound(const utri_graph* g, int64_t align);

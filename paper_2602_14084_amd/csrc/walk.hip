@@ -18,11 +18,14 @@
 // {x, y} is streamed from x's side (see k_items).
 //
 // GPU mapping (persistent grid, two phases per work-group, atomic work queues):
-//   * long staged rows (len > CAP = 128): one work-group per item (x, CAPH = 2048-entry
-//     chunk, partner range); the chunk of N+(x) is staged in a work-group LDS table and
-//     the work-group's waves take the partners round-robin (on R-MAT s23 these items
-//     carry 98% of the streamed ids);
+//   * long staged rows (len > cap): one work-group per item (x, chunk of caph entries,
+//     partner range); the chunk of N+(x) is staged in a work-group LDS table and the
+//     work-group's waves take the partners round-robin (on R-MAT s23 these items carry
+//     98% of the streamed ids);
 //   * other staged rows: one wave per item, the row staged in the wave's own table.
+//   cap (at most CAP = 128), caph (at most CAPH = 2048), the partners per item, the loads
+//   in flight and the shorter-row crossover are run-time launch parameters (WalkTune) that
+//   the autotuner picks per graph; the defaults are 128, 2048, 1024, 8 and 320.
 //   A table is open addressing over buckets of four slots with two parallel arrays: the
 //   staged ids (0 = empty) and, per slot, a word holding the entry's d code, its position
 //   in the row and a presence bit. A probe reads one bucket of each with two 16-byte LDS
@@ -56,7 +59,7 @@ namespace {
 #ifndef UTRI_WALK_WAVE_LG
 #define UTRI_WALK_WAVE_LG 7
 #endif
-constexpr int CAPH = UTRI_WALK_CAPH;  // staged entries per work-group item (one chunk of a row)
+constexpr int CAPH = UTRI_WALK_CAPH;  // most entries of one work-group table chunk
 constexpr int NW_MAX = 8;             // enumeration slots per heavy item (one per wave)
 constexpr int WAVE_LG = UTRI_WALK_WAVE_LG;  // wave tables: 2^WAVE_LG buckets of 4 slots
 static_assert(CAP <= (4 << WAVE_LG), "wave tables hold CAP entries");
@@ -71,10 +74,6 @@ static_assert(CAPH < 32768, "positions are 15-bit in the table words");
 #ifndef UTRI_WALK_UNR_MAX
 #define UTRI_WALK_UNR_MAX 8        // loads in flight per lane on long streamed rows
 #endif
-#ifndef UTRI_WALK_PR
-#define UTRI_WALK_PR 1024          // symmetric-row entries (partners) per item
-#endif
-constexpr int PR = UTRI_WALK_PR;
 #ifndef UTRI_WALK_SHORTER
 #define UTRI_WALK_SHORTER 1        // 1: each edge streams the shorter kept row; 0: always N+(v)
 #endif
@@ -198,15 +197,15 @@ __device__ __forceinline__ uint32_t tab_find(const uint32_t* key, uint32_t bmask
 }
 
 // Items. Every vertex x with a kept oriented row of len >= 2 stages (chunks of) N+(x) as a
-// table and streams, for each partner y (a kept neighbour of x, in ranges of PR entries of
+// table and streams, for each partner y (a kept neighbour of x, in ranges of pr entries of
 // the symmetric row), the kept row N+(y) through it. Each kept edge {x, y} is streamed
 // from exactly one side: the shorter kept row goes through the longer one's table (ties:
 // the row of the higher-ranked end through the lower one's table, as in the plain forward
 // iteration). Either way w runs over N+(u) ∩ N+(v) for the oriented edge u -> v, so the
 // triangles visited are those of Section 4, once each. Item word: vertex in bits 0-30,
 // table chunk in bits 32-42, partner range in bits 43-63.
-//   light items: 2 <= len <= CAP, one per partner range;
-//   heavy items: len > CAP, one per (chunk of CAPH entries, partner range).
+//   light items: 2 <= len <= cap, one per partner range;
+//   heavy items: len > cap, one per (chunk of caph entries, partner range).
 __host__ __device__ inline int64_t item_word(int64_t v, int64_t chunk, int64_t range) {
     return (int64_t)(((uint64_t)range << 43) | ((uint64_t)chunk << 32) | (uint64_t)v);
 }
@@ -214,19 +213,16 @@ __device__ inline int item_vertex(int64_t it) { return (int)(it & 0x7FFFFFFF); }
 __device__ inline int item_chunk(int64_t it) { return (int)(((uint64_t)it >> 32) & 0x7FF); }
 __device__ inline int item_range(int64_t it) { return (int)((uint64_t)it >> 43); }
 constexpr int64_t MAX_CHUNKS = 2048;
-__host__ __device__ inline int partner_ranges(int32_t sl) {
-    return sl > PR ? (int)(((int64_t)sl + PR - 1) / PR) : 1;
+__host__ __device__ inline int partner_ranges(int32_t sl, int pr) {
+    return sl > pr ? (int)(((int64_t)sl + pr - 1) / pr) : 1;
 }
 
 // Streaming the shorter row pays when the rows the plain forward iteration streams are
 // long: it then skips most of their strips, while scanning both ends' symmetric rows for
 // partners costs about the same per edge either way. When the plain iteration would
-// stream fewer than UTRI_WALK_SHORTER_MIN ids per kept edge on average, and for the
-// sign-world walk (whose mask reads follow the staged row), items stream N+(v) for the v
-// of their own row (only the first partner range of an item has work then).
-#ifndef UTRI_WALK_SHORTER_MIN
-#define UTRI_WALK_SHORTER_MIN 320
-#endif
+// stream fewer than tune.shorter_min ids per kept edge on average, and for the sign-world
+// walk (whose mask reads follow the staged row), items stream N+(v) for the v of their
+// own row (only the first partner range of an item has work then).
 // The two totals are accumulated in KEPT_SLOTS slot pairs, 128 bytes apart, after the
 // four item counters (atomics on one address serialise).
 constexpr int KEPT_SLOTS = 64;
@@ -242,18 +238,36 @@ __device__ inline bool stream_shorter(const WalkParams& wp, const int64_t* n_ite
         kept += n_items_dev[4 + i * KEPT_STRIDE];
         plain += n_items_dev[5 + i * KEPT_STRIDE];
     }
-    return (double)plain >= (double)UTRI_WALK_SHORTER_MIN * (double)kept;
+    return (double)plain >= (double)wp.tune.shorter_min * (double)kept;
 }
 
 // Bounds of the two item lists (a kept symmetric row of sl entries has at most
-// 1 + sl / PR ranges; the symmetric rows hold 2m entries).
-inline int64_t chunks_bound(const utri_graph* g) { return (g->max_out + CAPH - 1) / CAPH + 1; }
+// 1 + sl / pr ranges; the symmetric rows hold 2m entries).
+inline int64_t chunks_bound(const utri_graph* g) {
+    const int64_t caph = g->walk_tune.caph;
+    return (g->max_out + caph - 1) / caph + 1;
+}
 inline int64_t light_bound(const utri_graph* g) {
-    return std::min<int64_t>(g->n, g->m / 2) + 2 * g->m / PR + 1;
+    return std::min<int64_t>(g->n, g->m / 2) + 2 * g->m / g->walk_tune.pr + 1;
 }
 inline int64_t heavy_bound(const utri_graph* g) {
-    return g->m / CAPH + g->m / CAP + chunks_bound(g) * (g->m / CAP + 2 * g->m / PR + 1) + 2;
+    const WalkTune& t = g->walk_tune;
+    return g->m / t.caph + g->m / t.cap + chunks_bound(g) * (g->m / t.cap + 2 * g->m / t.pr + 1) + 2;
 }
+
+}  // namespace
+
+// Whether run-time launch parameters fit the compiled table geometry.
+bool utri_walk_tune_ok(const WalkTune& t) {
+    const auto pow2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
+    return t.pr >= UTRI_WAVE && t.pr <= (1 << 20) && t.pr % UTRI_WAVE == 0 && pow2(t.cap) &&
+           t.cap >= 8 && t.cap <= CAP && pow2(t.caph) && t.caph >= std::max(t.cap, 256) &&
+           t.caph <= CAPH &&
+           (t.unr == 1 || t.unr == 2 || t.unr == 4 || t.unr == 8) && t.shorter_min >= 0 &&
+           t.shorter_min <= ((int64_t)1 << 40);
+}
+
+namespace {
 
 // Kept prefixes at c of the oriented row (len) and of the symmetric row (slen) of each
 // vertex, and its light and heavy item counts. Over the slot pairs, kept[.][0] sums to the
@@ -281,7 +295,7 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
                          int64_t n, double c, int32_t* __restrict__ len,
                          int32_t* __restrict__ slen, int32_t* __restrict__ lcnt,
                          int32_t* __restrict__ hcnt, unsigned long long* __restrict__ kept,
-                         uint2* __restrict__ rinfo) {
+                         uint2* __restrict__ rinfo, int cap, int caph, int pr) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t L = 0, SL = 0;
     if (v < n) {
@@ -308,22 +322,22 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
     len[v] = L;
     slen[v] = SL;
     rinfo[v] = make_uint2((uint32_t)off[v], (uint32_t)L);
-    const int nr = partner_ranges(SL);
-    lcnt[v] = (L >= 2 && L <= CAP) ? nr : 0;
-    hcnt[v] = (L > CAP) ? ((L + CAPH - 1) / CAPH) * nr : 0;
+    const int nr = partner_ranges(SL, pr);
+    lcnt[v] = (L >= 2 && L <= cap) ? nr : 0;
+    hcnt[v] = (L > cap) ? ((L + caph - 1) / caph) * nr : 0;
 }
 
 __global__ void k_items(const int32_t* __restrict__ lcnt, const int32_t* __restrict__ hcnt,
                         const int32_t* __restrict__ slen, const int64_t* __restrict__ loff,
                         const int64_t* __restrict__ hoff, int64_t n, int64_t hbase,
-                        int64_t* __restrict__ items) {
+                        int64_t* __restrict__ items, int pr) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int nl = lcnt[v];
     for (int r = 0; r < nl; r++) items[loff[v] + r] = item_word(v, 0, r);
     const int nh = hcnt[v];
     if (nh == 0) return;
-    const int nr = partner_ranges(slen[v]);
+    const int nr = partner_ranges(slen[v], pr);
     const int64_t o = hbase + hoff[v];
     for (int k = 0; k < nh; k++) items[o + k] = item_word(v, k / nr, k % nr);
 }
@@ -650,15 +664,15 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const double* _
 #if UTRI_WALK_UNR_MAX >= 8
     // the sign-world walk keeps its counter planes in registers: eight loads ahead would
     // spill them
-    if (MODE != WALK_SIGN && lvs > 4 * UTRI_WAVE)
+    if (MODE != WALK_SIGN && lvs > 4 * UTRI_WAVE && wp.tune.unr >= 8)
         stream_row<MODE, 8, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
                                   run_b, run_u);
     else
 #endif
-    if (lvs > 2 * UTRI_WAVE)
+    if (lvs > 2 * UTRI_WAVE && wp.tune.unr >= 4)
         stream_row<MODE, 4, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
                                   run_b, run_u);
-    else if (lvs > UTRI_WAVE)
+    else if (lvs > UTRI_WAVE && wp.tune.unr >= 2)
         stream_row<MODE, 2, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
                                   run_b, run_u);
     else
@@ -755,7 +769,7 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
     }
 }
 
-// Wave item: vertex u with 2 <= len <= CAP, N+(u) staged in the wave's own table, and
+// Wave item: vertex u with 2 <= len <= cap, N+(u) staged in the wave's own table, and
 // one range of its partners.
 template <int MODE, bool shorter, class G>
 __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
@@ -769,8 +783,9 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const int rg = item_range(item);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
-    const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * PR : ou;
-    const int np = shorter ? min(PR, wp.slen[u] - rg * PR) : (rg == 0 ? Lu : 0);
+    const int pr = wp.tune.pr;
+    const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * pr : ou;
+    const int np = shorter ? min(pr, wp.slen[u] - rg * pr) : (rg == 0 ? Lu : 0);
     if (np <= 0) return;  // (the enumeration slots start zeroed)
     const int lg = tab_lg(Lu, G::WLG);
     tab_clear<WOFF>(L.key, lg, lane, UTRI_WAVE);
@@ -796,7 +811,7 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     utri_wave_sync();
 }
 
-// Work-group item: chunk `chunk` (CAPH entries) of a long source row, one shared table,
+// Work-group item: chunk `chunk` (caph entries) of a long source row, one shared table,
 // target rows split round-robin over the waves. Enumeration slots are per wave.
 template <int MODE, bool shorter, class G>
 __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict__ o_off,
@@ -812,11 +827,12 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     const int rg = item_range(item);
     const int64_t ou = o_off[u];
     const int Lu = len[u];
-    const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * PR : ou;
-    const int np = shorter ? min(PR, wp.slen[u] - rg * PR) : (rg == 0 ? Lu : 0);
+    const int pr = wp.tune.pr;
+    const int64_t sb = shorter ? wp.s_off[u] + (int64_t)rg * pr : ou;
+    const int np = shorter ? min(pr, wp.slen[u] - rg * pr) : (rg == 0 ? Lu : 0);
     if (np <= 0) return;  // work-group uniform (the enumeration slots start zeroed)
-    const int cb = chunk * CAPH;
-    const int cl = min(CAPH, Lu - cb);
+    const int cb = chunk * wp.tune.caph;
+    const int cl = min(wp.tune.caph, Lu - cb);
     const int lg = tab_lg(cl, G::LGH);
     __syncthreads();  // the previous item's probes are done
     tab_clear<WOFF>(B.key, lg, threadIdx.x, G::TPBW);
@@ -1029,14 +1045,32 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     int32_t* slen = (int32_t*)plen + n + 1;
     hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, g->s_off,
                        g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt,
-                       (unsigned long long*)pn + 4, (uint2*)pri);
+                       (unsigned long long*)pn + 4, (uint2*)pri, g->walk_tune.cap,
+                       g->walk_tune.caph, g->walk_tune.pr);
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
     UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
     hipLaunchKernelGGL(k_items, dim3(blocks_for(n)), dim3(TPB), 0, s, (const int32_t*)lcnt,
                        (const int32_t*)hcnt, (const int32_t*)slen, (const int64_t*)loff,
-                       (const int64_t*)hoff, n, lb, (int64_t*)pitems);
+                       (const int64_t*)hoff, n, lb, (int64_t*)pitems, g->walk_tune.pr);
     UTRI_HIP_TRY(hipGetLastError());
+    return UTRI_OK;
+}
+
+// Ids the plain forward iteration streams per kept oriented edge at the last prepared
+// query (the ratio the shorter-row crossover is compared with); waits for the stream.
+int utri_walk_plain_ratio(utri_graph* g, hipStream_t s, double* ratio) {
+    void* pn;
+    UTRI_TRY(utri_scratch(g, SCR_NITEMS, sizeof(int64_t) * NITEMS_WORDS, &pn));
+    int64_t h[NITEMS_WORDS];
+    UTRI_HIP_TRY(hipMemcpyAsync(h, pn, sizeof(h), hipMemcpyDeviceToHost, s));
+    UTRI_HIP_TRY(hipStreamSynchronize(s));
+    int64_t kept = 0, plain = 0;
+    for (int i = 0; i < KEPT_SLOTS; i++) {
+        kept += h[4 + i * KEPT_STRIDE];
+        plain += h[5 + i * KEPT_STRIDE];
+    }
+    *ratio = kept > 0 ? (double)plain / (double)kept : 0.0;
     return UTRI_OK;
 }
 
@@ -1045,6 +1079,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
 static void set_launch_fields(utri_graph* g, WalkParams& wp, const int32_t* len) {
     wp.lb = light_bound(g);
     wp.order = g->walk_order;
+    wp.tune = g->walk_tune;
     wp.s_off = g->s_off;
     wp.s_adj = g->s_adj;
     wp.s_d = g->s_d;

@@ -38,7 +38,12 @@ ABI_FUNCTIONS = [
     "utri_graph_set_p", "utri_count", "utri_count_batch", "utri_enumerate", "utri_expected",
     "utri_expected_grad", "utri_edge_local", "utri_vertex_local", "utri_topk", "utri_sign_worlds", "utri_sample", "utri_batch", "utri_autotune", "utri_set_walk_order",
     "utri_walk_stats", "utri_timing", "utri_strerror", "utri_count_noalloc",
+    "utri_get_tuning", "utri_set_tuning",
 ]
+
+# launch parameters, in the order of utri_get_tuning / utri_set_tuning
+TUNE_NAMES = ["walk_blocks_per_cu", "sample_chunk", "walk_partners", "walk_light_cap",
+              "walk_chunk", "walk_unroll", "walk_shorter_min"]
 
 _lib = None
 
@@ -79,6 +84,8 @@ def lib():
     L.utri_batch.argtypes = [vp, P(f64), C.c_int, i64, i32, u64, vp, vp, C.c_int, vp]
     L.utri_autotune.argtypes = [vp, f64, C.c_char_p, vp]
     L.utri_set_walk_order.argtypes = [vp, C.c_int]
+    L.utri_get_tuning.argtypes = [vp, P(i64)]
+    L.utri_set_tuning.argtypes = [vp, P(i64)]
     L.utri_walk_stats.argtypes = [vp, f64, C.c_int, P(i64), vp]
     L.utri_timing.argtypes = [vp, C.c_int, P(f64), P(i64)]
     L.utri_strerror.argtypes = [C.c_int]
@@ -311,6 +318,24 @@ def utri_set_walk_order(h, order):
     _check(lib().utri_set_walk_order(h, int(order)), "utri_set_walk_order")
 
 
+def utri_get_tuning(h):
+    """dict of the handle's launch parameters (names in TUNE_NAMES)."""
+    out = (C.c_int64 * len(TUNE_NAMES))()
+    _check(lib().utri_get_tuning(h, out), "utri_get_tuning")
+    return dict(zip(TUNE_NAMES, [int(x) for x in out]))
+
+
+def utri_set_tuning(h, **kw):
+    """Set some launch parameters by name; the others keep their current values."""
+    cur = utri_get_tuning(h)
+    for k, v in kw.items():
+        if k not in cur:
+            raise KeyError(k)
+        cur[k] = int(v)
+    arr = (C.c_int64 * len(TUNE_NAMES))(*[cur[k] for k in TUNE_NAMES])
+    _check(lib().utri_set_tuning(h, arr), "utri_set_tuning")
+
+
 def utri_walk_stats(h, t, method=UTRI_PRUNED, stream=None):
     """dict(m_c, target_elems, candidates, streamed, items) of one counting walk at t."""
     out = (C.c_int64 * 5)()
@@ -415,6 +440,12 @@ class Graph:
 
     def autotune(self, t, cache_path=None):
         utri_autotune(self._h, t, cache_path)
+
+    def tuning(self):
+        return utri_get_tuning(self._h)
+
+    def set_tuning(self, **kw):
+        utri_set_tuning(self._h, **kw)
 
 
 def _make_expected_balanced():

@@ -6,6 +6,8 @@ equality (the 1e-12 relative bound on E is met with room to spare); sampler
 estimates replay the same Philox draws and are compared exactly. Sizes span several
 work items (rows cut into 512-entry chunks, many 64-lane strips) and ragged tails.
 """
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -470,21 +472,86 @@ def test_sweeps_quick(tmp_path):
 
 def test_autotune_keeps_results_and_caches(monkeypatch, tmp_path):
     # tuning only picks launch shapes: every result stays the oracle's; the choice is
-    # written to the cache and a later handle of the same graph reads it back
+    # written to the cache, a later autotune of the same graph shape takes it without
+    # timing, and a handle created with UTRI_TUNE_CACHE set starts from it
     n, lo, hi = inputs.rmat_graph(12, seed=3)
     p = inputs.draw_p(lo.shape[0], "uniform", 21)
     og = oracle.load(n, lo, hi, p)
     g = gpu_graph(n, lo, hi, p)
+    assert g.tuning() == {"walk_blocks_per_cu": 0, "sample_chunk": 128, "walk_partners": 1024,
+                          "walk_light_cap": 128, "walk_chunk": 2048, "walk_unroll": 8,
+                          "walk_shorter_min": 320}
     cache = tmp_path / "tune.jsonl"
     say("autotune rmat12")
     g.autotune(0.7, str(cache))
+    chosen = g.tuning()
     assert g.count(0.7) == tuple(og.count(0.7))
     assert np.array_equal(g.sample([0.7], 500, 4, 3).cpu().numpy(), og.sample([0.7], 500, 4, 3)[0])
-    text = cache.read_text()
-    assert "walk_blocks_per_cu" in text and "sample_chunk" in text
-    monkeypatch.setenv("UTRI_TUNE_CACHE", str(cache))
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert rec["n"] == n and all(rec[k] == v for k, v in chosen.items())
+    # a second handle of the same shape: autotune applies the cached line, appends nothing
     g2 = gpu_graph(n, lo, hi, p)
-    assert g2.count(0.8) == tuple(og.count(0.8))
+    g2.autotune(0.9, str(cache))
+    assert g2.tuning() == chosen
+    assert len(cache.read_text().strip().splitlines()) == 1
+    monkeypatch.setenv("UTRI_TUNE_CACHE", str(cache))
+    g3 = gpu_graph(n, lo, hi, p)
+    assert g3.tuning() == chosen
+    assert g3.count(0.8) == tuple(og.count(0.8))
+    # another graph shape does not match the cached line
+    n4, lo4, hi4 = inputs.rmat_graph(11, seed=3)
+    g4 = gpu_graph(n4, lo4, hi4, inputs.draw_p(lo4.shape[0], "uniform", 21))
+    assert g4.tuning()["walk_partners"] == 1024 and g4.tuning()["walk_chunk"] == 2048
+
+
+@pytest.mark.parametrize("knob,values", [
+    ("walk_partners", [64, 256, 4096]),
+    ("walk_light_cap", [8, 32]),
+    ("walk_chunk", [256, 512]),
+    ("walk_unroll", [1, 2, 4]),
+    ("walk_shorter_min", [0, 1 << 40]),
+    ("walk_blocks_per_cu", [1, 7]),
+])
+def test_walk_tuning_keeps_results(knob, values):
+    # every launch parameter value the autotuner may pick gives the oracle's counts,
+    # threshold histogram, enumeration and expected count (R-MAT 15: rows of every owner
+    # class, long rows cut into several chunks at the small chunk sizes)
+    n, lo, hi = inputs.rmat_graph(15, seed=4)
+    p = inputs.draw_p(lo.shape[0], "beta22", 5)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    ts = [0.5, 0.7, 0.9]
+    want = og.count_multi(ts)
+    want_e = og.expected()[0]
+    ob, ou = og.enumerate(0.7)
+    for v in values:
+        say(f"tuning {knob}={v}")
+        g.set_tuning(**{knob: v})
+        assert g.tuning()[knob] == v
+        for j, t in enumerate(ts):
+            for method in (utri.UTRI_PLAIN, utri.UTRI_PRUNED, utri.UTRI_PRUNED_L3):
+                assert g.count(t, method) == tuple(want[j]), (knob, v, t, method)
+        assert np.array_equal(g.count_batch(ts), want), (knob, v)
+        bal, unb = g.enumerate(0.7, sorted=True)
+        assert np.array_equal(bal.cpu().numpy(), ob) and np.array_equal(unb.cpu().numpy(), ou)
+        assert g.expected() == want_e, (knob, v)
+    g.set_tuning(walk_partners=1024, walk_light_cap=128, walk_chunk=2048, walk_unroll=8,
+                 walk_shorter_min=320, walk_blocks_per_cu=0)
+
+
+def test_walk_tuning_rejects_bad_values():
+    n, lo, hi = inputs.rmat_graph(10, seed=1)
+    g = gpu_graph(n, lo, hi, inputs.draw_p(lo.shape[0], "uniform", 1))
+    before = g.tuning()
+    for kw in ({"walk_partners": 100}, {"walk_partners": 0}, {"walk_light_cap": 256},
+               {"walk_light_cap": 48}, {"walk_chunk": 4096}, {"walk_chunk": 128},
+               {"walk_unroll": 3}, {"walk_shorter_min": -1}, {"sample_chunk": 100},
+               {"walk_blocks_per_cu": 65}):
+        with pytest.raises(utri.UtriError):
+            g.set_tuning(**kw)
+        assert g.tuning() == before
 
 
 def test_batch_eager_and_graph_replays():
