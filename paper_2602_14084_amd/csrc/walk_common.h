@@ -222,6 +222,17 @@ static_assert((SCAP & (SCAP - 1)) == 0 && (SCAPH & (SCAPH - 1)) == 0 && SCAP <= 
                   SCAPH <= 65536,
               "table sizes are powers of two; positions are 16-bit");
 
+// Hub groups probe y's global table; a one-hash bit filter of y's prefix, in the LDS that
+// the work-group tables use otherwise (SF_BITS bits), sends only the entries whose bit is
+// set there to the table.
+#ifndef UTRI_SAMPLE_FILTER
+#define UTRI_SAMPLE_FILTER 1
+#endif
+constexpr uint32_t SF_BITS = (uint32_t)SCAPH * SSL * 48;  // key and pos arrays: 6 bytes per slot
+__device__ __forceinline__ uint32_t sample_filter_bit(int32_t w) {
+    return __umulhi((uint32_t)w * 0x9E3779B1u, SF_BITS);
+}
+
 struct SampleWaveLds {
     alignas(16) int32_t key[SCAP * SSL];  // neighbour id + 1 (0 = empty)
     uint16_t pos[SCAP * SSL];
@@ -287,16 +298,26 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
         bool hit[UNR];
         double dy[UNR];
         if (GLOBAL_TABLE) {
-            // lg: log2 of the bucket count; a hit reads d from the slot
+            // lg: log2 of the bucket count; a hit reads d from the slot; key: the filter
             const uint32_t gm = (1u << lg) - 1u;
             uint32_t b[UNR];
             uint4 k0[UNR], k1[UNR];
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
                 b[k] = utri_hbucket(w[k], lg);
-                const uint4* p = hbucket_ptr(G.h_key, hoff, b[k]);
-                k0[k] = p[0];
-                k1[k] = p[1];
+                bool cand = true;
+#if UTRI_SAMPLE_FILTER
+                const uint32_t fb = sample_filter_bit(w[k]);
+                cand = ((reinterpret_cast<const uint32_t*>(key)[fb >> 5] >> (fb & 31u)) & 1u) != 0u;
+#endif
+                // an all-empty bucket matches nothing and ends the search
+                k0[k] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+                k1[k] = k0[k];
+                if (cand) {
+                    const uint4* p = hbucket_ptr(G.h_key, hoff, b[k]);
+                    k0[k] = p[0];
+                    k1[k] = p[1];
+                }
             }
 #pragma unroll
             for (int k = 0; k < UNR; k++) {
@@ -414,9 +435,19 @@ __device__ inline void sample_item(const SampleParams& sp, const SampleGraph& G,
         const int hlg = hbuckets_lg(G, y);
         __syncthreads();  // the previous item's flushes are done
         for (int q = threadIdx.x; q < WPB * 2 * NB; q += TPB) (&B.rh[0][0][0])[q] = 0;
+        uint32_t* bits = reinterpret_cast<uint32_t*>(B.key);
+#if UTRI_SAMPLE_FILTER
+        for (int i = threadIdx.x; i < (int)(SF_BITS / 32); i += TPB) bits[i] = 0u;
         __syncthreads();
-        group_draws<true>(sp, G, slen, y, r0, r1, nullptr, nullptr, hlg, 0, hoff, B.rh[wib], wib,
-                          WPB);
+        const int64_t sy = G.s_off[y];
+        for (int j = threadIdx.x; j < Ly; j += TPB) {
+            const uint32_t fb = sample_filter_bit(G.s_adj[sy + j]);
+            atomicOr(&bits[fb >> 5], 1u << (fb & 31u));
+        }
+#endif
+        __syncthreads();
+        group_draws<true>(sp, G, slen, y, r0, r1, (const int32_t*)bits, nullptr, hlg, 0, hoff,
+                          B.rh[wib], wib, WPB);
         return;
     }
     if (block) {
