@@ -589,6 +589,14 @@ int utri_sign_worlds(utri_graph* g, int32_t worlds, uint64_t seed, int64_t* coun
     UTRI_TRY(utri_scratch(g, SCR_SIGN_CNT, sizeof(uint64_t) * (size_t)worlds, &pc));
     UTRI_TRY(utri_fill_u64(pc, 0, worlds, s));
     UTRI_TRY(utri_sign_masks_launch(g, seed, ww, (uint32_t*)pm, s));
+    // the sign-world walk's work-group table holds chunks of at most UTRI_SIGN_WALK_CHUNK
+    // entries: its items are cut that way for this call
+    struct TuneScope {
+        utri_graph* g;
+        WalkTune saved;
+        ~TuneScope() { g->walk_tune = saved; }
+    } scope{g, g->walk_tune};
+    g->walk_tune.caph = std::min(g->walk_tune.caph, UTRI_SIGN_WALK_CHUNK);
     int64_t *items, *nitems;
     int32_t* len;
     UTRI_TRY(utri_walk_prepare(g, 0.0, 0, s, &items, &nitems, &len));

@@ -144,6 +144,10 @@ struct WalkTune {
     }
 };
 
+// Longest work-group table chunk of the sign-world walk (its work-groups keep a smaller
+// table so that more of them fit a compute unit).
+constexpr int UTRI_SIGN_WALK_CHUNK = 1024;
+
 struct UtriBatchGraph {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;

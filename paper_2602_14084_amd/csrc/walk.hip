@@ -362,7 +362,8 @@ struct WalkLaneState {
 struct SignQueue {
     int32_t e[3][SIGN_Q];
 };
-__shared__ SignQueue sign_q[NW_MAX];
+constexpr int SIGN_NW = 4;  // waves per work-group of the sign-world walk
+__shared__ SignQueue sign_q[SIGN_NW];
 
 // Add this lane's 32 counters into the per-world totals and clear them.
 __device__ __forceinline__ void sign_flush(const WalkParams& wp, WalkLaneState& st) {
@@ -941,8 +942,24 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
     }
 }
 
+// Geometry of each walk kernel: the sign-world walk keeps its counter planes in registers
+// (about 96 VGPRs, five waves per SIMD), so it runs four-wave work-groups with a smaller
+// work-group table (chunks of at most UTRI_SIGN_WALK_CHUNK entries), which fill those five
+// wave slots; the other walks run eight waves per group within 64 VGPRs.
 template <int MODE>
-__global__ void __launch_bounds__(GeomWalk::TPBW, UTRI_WALK_MIN_WAVES) k_walk(WalkParams wp,
+struct WalkGeom {
+    using G = GeomWalk;
+    static constexpr int MIN_WAVES = UTRI_WALK_MIN_WAVES;
+};
+template <>
+struct WalkGeom<WALK_SIGN> {
+    using G = Geom<SIGN_NW, 9, WAVE_LG>;
+    static constexpr int MIN_WAVES = 1;
+    static_assert(2 * (1 << G::LGH) >= UTRI_SIGN_WALK_CHUNK, "chunks fit the table");
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(WalkGeom<MODE>::G::TPBW, WalkGeom<MODE>::MIN_WAVES) k_walk(WalkParams wp,
                                                           const int64_t* __restrict__ o_off,
                                                           const int32_t* __restrict__ o_adj,
                                                           const double* __restrict__ o_d,
@@ -951,7 +968,7 @@ __global__ void __launch_bounds__(GeomWalk::TPBW, UTRI_WALK_MIN_WAVES) k_walk(Wa
                                                           const int32_t* __restrict__ perm,
                                                           const int64_t* __restrict__ items,
                                                           const int64_t* __restrict__ n_items_dev) {
-    using G = GeomWalk;
+    using G = typename WalkGeom<MODE>::G;
     __shared__ WalkShared<G> S;
     __shared__ HistLds hlds[MODE == WALK_HIST ? G::NW : 1];
     const int wib = threadIdx.x / UTRI_WAVE;
@@ -1126,7 +1143,7 @@ static int blocks_per_cu(utri_graph* g, K kernel, int tpb) {
 template <int MODE>
 static void launch_walk(utri_graph* g, const WalkParams& wp, const int32_t* len,
                         const int64_t* items, const int64_t* n_items_dev, hipStream_t s) {
-    const int tpb = GeomWalk::TPBW;
+    const int tpb = WalkGeom<MODE>::G::TPBW;
     const int blocks = g->num_cu * blocks_per_cu(g, k_walk<MODE>, tpb);
     hipLaunchKernelGGL(k_walk<MODE>, dim3(blocks), dim3(tpb), 0, s, wp, g->o_off, g->o_adj,
                        g->o_d, len, (const uint2*)g->rinfo_cur, g->perm, items, n_items_dev);
