@@ -136,7 +136,8 @@ int sort_triples(utri_graph* g, int32_t* tri, int64_t cnt, hipStream_t s) {
 int walk_prepare_for(utri_graph* g, int method, double c, hipStream_t s, int64_t** items,
                      int64_t** nitems, int32_t** len) {
     const double c_rows = (method == UTRI_PLAIN) ? 0.0 : c;
-    return utri_walk_prepare(g, c_rows, 0, s, items, nitems, len);
+    return utri_walk_prepare(g, c_rows, (method == UTRI_PRUNED_L3 && c > 0.0) ? 1 : 0, s, items,
+                             nitems, len);
 }
 
 WalkParams base_params(int method, double c) {

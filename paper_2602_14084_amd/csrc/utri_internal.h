@@ -406,7 +406,7 @@ __device__ inline int64_t utri_sample_vertex(uint64_t seed, uint32_t world, uint
 // ------------------------------------------------------------------ kernels (host launchers)
 
 // per-query preparation of the oriented walk
-int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int64_t** items,
+int utri_walk_prepare(utri_graph* g, double c_rows, int lemma3, hipStream_t s, int64_t** items,
                       int64_t** n_items_dev, int32_t** len);
 
 enum WalkMode {

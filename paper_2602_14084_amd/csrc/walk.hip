@@ -288,14 +288,17 @@ __device__ __forceinline__ int32_t kept_prefix(const int64_t* __restrict__ off,
     return (int32_t)(lo - a);
 }
 
-// Also writes rinfo[v] = (start of N+(v) in o_adj, kept length): what a partner scan reads
-// about each partner, in one 8-byte load (m < 2^31, so row starts fit 32 bits).
+// Also writes rinfo[v] = (start of N+(v) in o_adj, kept length | q << 16): what a partner
+// scan reads about each partner, in one 8-byte load (m < 2^31, so row starts fit 32 bits,
+// and an oriented row has fewer than 2^16 entries); q = floor(|d| * 2^16) of the kept
+// row's last entry, a lower bound of every kept |d| that lets the Lemma-3 cut skip the
+// row end's exact d when the bound already keeps the whole row.
 __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restrict__ dd,
                          const int64_t* __restrict__ soff, const double* __restrict__ sd,
                          int64_t n, double c, int32_t* __restrict__ len,
                          int32_t* __restrict__ slen, int32_t* __restrict__ lcnt,
                          int32_t* __restrict__ hcnt, unsigned long long* __restrict__ kept,
-                         uint2* __restrict__ rinfo, int cap, int caph, int pr) {
+                         uint2* __restrict__ rinfo, int cap, int caph, int pr, int lemma3) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t L = 0, SL = 0;
     if (v < n) {
@@ -321,7 +324,9 @@ __global__ void k_rowlen(const int64_t* __restrict__ off, const double* __restri
     if (v >= n) return;
     len[v] = L;
     slen[v] = SL;
-    rinfo[v] = make_uint2((uint32_t)off[v], (uint32_t)L);
+    uint32_t q = 0;
+    if (lemma3 && L > 0) q = min((uint32_t)(fabs(dd[off[v] + L - 1]) * 65536.0), 65535u);
+    rinfo[v] = make_uint2((uint32_t)off[v], (uint32_t)L | (q << 16));
     const int nr = partner_ranges(SL, pr);
     lcnt[v] = (L >= 2 && L <= cap) ? nr : 0;
     hcnt[v] = (L > cap) ? ((L + caph - 1) / caph) * nr : 0;
@@ -633,51 +638,64 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
     }
 }
 
-// Stream the kept target row [ovs, ovs + lvs) of v, UNR strips of loads in flight.
-template <int MODE, int UNR, int WOFF>
+// Stream the kept target row [ovs, ovs + lvs) of v, UNR strips of loads in flight. q3 > 0
+// (a row the Lemma-3 cut may shorten, see load_partners) stops the stream after the first
+// batch whose last entry has code q with q + 1 <= q3: that entry, and every later one (the
+// row is in |d| order), fails the cut, and the triangles of the entries that fail it are
+// unclassifiable, streamed or not.
+template <int MODE, int UNR, int WOFF, bool L3>
 __device__ __forceinline__ void stream_row(const WalkParams& wp, const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const TabRef& R,
                                            int64_t ovs, int lvs, double duvs, int32_t pv,
-                                           const CodeRow& cr, int si, double duv_lanes,
+                                           const CodeRow& cr, int si, double duv_lanes, int q3,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
     (void)duv_lanes;
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(wp, ovs, lvs);
+    int covered = lvs;
     for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
         uint32_t pw[UNR];
         load_strips<UNR>(rs, j0, pw);  // all UNR loads are issued before any probe
         probe_strips<MODE, UNR, WOFF>(wp, o_d, perm, R, pw, j0, ovs, lvs, duvs, pv, cr, si, H, st,
                                       run_b, run_u);
+        if (L3 && q3 > 0 && j0 + UNR * UTRI_WAVE < lvs) {
+            const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)pw[UNR - 1], UTRI_WAVE - 1);
+            const uint32_t qc = (wl >> wp.idbits) & ((1u << wp.mb) - 1u);
+            if ((int)qc + 1 <= q3) {
+                covered = j0 + UNR * UTRI_WAVE;
+                break;
+            }
+        }
     }
     if (MODE == WALK_STATS && utri_lane() == 0) {
-        st.wt_all += (uint64_t)lvs;
-        if (R.chunk == 0) st.wt += (uint64_t)lvs;
+        st.wt_all += (uint64_t)covered;
+        if (R.chunk == 0) st.wt += (uint64_t)covered;
     }
 }
 
-template <int MODE, int WOFF>
+template <int MODE, int WOFF, bool L3>
 __device__ __forceinline__ void stream_any(const WalkParams& wp, const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const TabRef& R,
                                            int64_t ovs, int lvs, double duvs, int32_t pv,
-                                           const CodeRow& cr, int si, double duv_lanes,
+                                           const CodeRow& cr, int si, double duv_lanes, int q3,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
 #if UTRI_WALK_UNR_MAX >= 8
     // the sign-world walk keeps its counter planes in registers: eight loads ahead would
     // spill them
     if (MODE != WALK_SIGN && lvs > 4 * UTRI_WAVE && wp.tune.unr >= 8)
-        stream_row<MODE, 8, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+        stream_row<MODE, 8, WOFF, L3>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, q3, H, st,
                                   run_b, run_u);
     else
 #endif
     if (lvs > 2 * UTRI_WAVE && wp.tune.unr >= 4)
-        stream_row<MODE, 4, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+        stream_row<MODE, 4, WOFF, L3>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, q3, H, st,
                                   run_b, run_u);
     else if (lvs > UTRI_WAVE && wp.tune.unr >= 2)
-        stream_row<MODE, 2, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+        stream_row<MODE, 2, WOFF, L3>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, q3, H, st,
                                   run_b, run_u);
     else
-        stream_row<MODE, 1, WOFF>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, H, st,
+        stream_row<MODE, 1, WOFF, L3>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, q3, H, st,
                                   run_b, run_u);
 }
 
@@ -685,13 +703,16 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const double* _
 // of x (np entries in this item's range; the waves of a work-group take every nparts-th
 // partner) with the start of N+(y), the kept length of N+(y) this item streams (0 when the
 // edge {x, y} is streamed from y's side, see k_items), d_xy and the edge id (sign worlds).
-template <int MODE, bool shorter>
+// PV: bit 0 = partners from the symmetric row (the shorter-row order), bit 1 = the
+// Lemma-3 cut is applied (its code is compiled only into the kernels that use it).
+template <int MODE, int PV>
 __device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
                                               const uint2* __restrict__ rinfo, int x, int Lx,
                                               int64_t sb, int np, int i0, int part, int nparts,
                                               double dmax_chunk, int& y, int64_t& oy, int& ly,
                                               double& dxy, int32_t& exy, CodeRow& cr) {
+    constexpr bool shorter = (PV & 1) != 0;
     const int i = i0 + utri_lane() * nparts + part;
     ly = 0; y = 0; oy = 0; dxy = 0.0; exy = 0;
     cr.khi = 0xFFFFFFFFu; cr.klo = 0u; cr.rsign = 0u;
@@ -699,23 +720,31 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_
         // shorter: entry of x's kept symmetric row; else: entry of N+(x) itself
         y = shorter ? wp.s_adj[sb + i] : (int)((uint32_t)o_adj[sb + i] & wp.idmask);
         const uint2 ri = rinfo[y];
-        const int L = (int)ri.y;
+        const int L = (int)(ri.y & 0xFFFFu);
         const bool mine = !shorter || ((y > x) ? (L <= Lx) : (L < Lx));
         if (mine && L > 0) {
             dxy = shorter ? wp.s_d[sb + i] : o_d[sb + i];
             oy = (int64_t)ri.x;
             ly = L;
-            if (wp.lemma3) {
-                // Lemma 3: keep w only if |d_yw| * (|d_xy| * max|d_xw|) >= c (with slack);
-                // the row is in |d| order, so nothing is cut when its last entry passes
+            if (PV & 2) {
+                // Lemma 3 keeps w only if |d_yw| * P >= c (with slack), P = |d_xy| *
+                // max|d_xw|. The row is in |d| order, so nothing is cut when its last entry
+                // passes, and it passes when the lower bound of its |d| does (rounding is
+                // monotonic). Otherwise ly carries, in bits 16 up, the code limit q3: an
+                // entry with code q (|d| <= (q + 1) 2^-mb) and q + 1 <= q3 fails the cut,
+                // since q3 <= c / P 2^mb - 2 keeps (q + 1) 2^-mb P below c by far more than
+                // the rounding of the product; c / P 2^mb is taken in FP32 with a hardware
+                // reciprocal, whose relative error (about 2^-21 in all) moves it by less
+                // than one of the two units of margin (a P too small for the margin gives
+                // q3 = 2^mb, and then every entry's |d| P <= P fails).
                 const double P = __dmul_rn(fabs(dxy), dmax_chunk);
-                if (__dmul_rn(fabs(o_d[oy + ly - 1]), P) < wp.c_l3) {
-                    int a = 0, b = ly;
-                    while (a < b) {
-                        const int mid = (a + b) >> 1;
-                        if (__dmul_rn(fabs(o_d[oy + mid]), P) >= wp.c_l3) a = mid + 1; else b = mid;
-                    }
-                    ly = a;
+                const double lb = (double)(ri.y >> 16) * 0x1p-16;
+                if (__dmul_rn(lb, P) < wp.c_l3) {
+                    const float qf = __builtin_amdgcn_rcpf((float)P) * (float)wp.c_l3 *
+                                     (float)(1 << wp.mb);
+                    const float qd = floorf(qf) - 2.0f;
+                    const int q3 = qd >= (float)(1 << wp.mb) ? (1 << wp.mb) : (qd > 0.0f ? (int)qd : 0);
+                    ly |= q3 << 16;
                 }
             }
             cr = code_row(wp, dxy);
@@ -731,7 +760,7 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_
 // Stream every partner row of one partner range of an item through the staged table;
 // partner p goes to the wave with p % nparts == part, which loads its own partners 64 at a
 // time.
-template <int MODE, bool shorter, int WOFF>
+template <int MODE, int PV, int WOFF>
 __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_t* __restrict__ o_adj,
                                               const double* __restrict__ o_d,
                                               const uint2* __restrict__ rinfo,
@@ -745,22 +774,24 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
         double duv;
         int32_t euv;
         CodeRow cr;
-        load_partners<MODE, shorter>(wp, o_adj, o_d, rinfo, u, Lu, sb, np, i0, part, nparts,
+        load_partners<MODE, PV>(wp, o_adj, o_d, rinfo, u, Lu, sb, np, i0, part, nparts,
                                      dmax_chunk, v, ov, lv, duv, euv, cr);
         // this wave's partners in the batch: i0 + part + nparts * si < np
         const int nv = min(UTRI_WAVE, (np - i0 - part + nparts - 1) / nparts);
         // lane by lane (a loop over the set bits of a ballot made the sign-world walk slower
         // and the others no faster)
         for (int si = 0; si < nv; si++) {
-            const int lvs = bcast_i32(lv, si);
+            const int lvm = bcast_i32(lv, si);
+            const int lvs = lvm & 0xFFFF;
             if (lvs == 0) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
                                : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
                               (uint32_t)bcast_i32((int)cr.klo, si),
                               (uint32_t)bcast_i32((int)cr.rsign, si)};
-            stream_any<MODE, WOFF>(wp, o_d, perm, R, bcast_i64(ov, si), lvs, bcast_f64(duv, si),
-                                   pv, crs, si, duv, H, st, run_b, run_u);
+            stream_any<MODE, WOFF, (PV & 2) != 0>(wp, o_d, perm, R, bcast_i64(ov, si), lvs,
+                                                  bcast_f64(duv, si), pv, crs, si, duv,
+                                                  (int)((uint32_t)lvm >> 16), H, st, run_b, run_u);
             if ((MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) && st.dn > DQ_DRAIN)
                 defer_drain(wp, o_d, R.src_base, duv, st);
         }
@@ -772,12 +803,13 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
 
 // Wave item: vertex u with 2 <= len <= cap, N+(u) staged in the wave's own table, and
 // one range of its partners.
-template <int MODE, bool shorter, class G>
+template <int MODE, int PV, class G>
 __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                const int32_t* __restrict__ len, const uint2* __restrict__ rinfo,
                                const int32_t* __restrict__ perm, int64_t item, int64_t it,
                                WaveTab<G>& L, HistLds* H, WalkLaneState& st) {
+    constexpr bool shorter = (PV & 1) != 0;
     constexpr int WOFF = 4 << G::WLG;
     const int lane = utri_lane();
     const int u = item_vertex(item);
@@ -797,7 +829,7 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     const double dmax_chunk = fabs(o_d[ou]);
     int64_t run_b = 0, run_u = 0;
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[it]; run_u = wp.off_u[it]; }
-    walk_partners<MODE, shorter, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
+    walk_partners<MODE, PV, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
                                        0, 1, H, st, run_b, run_u);
     // an item counts at most its candidates per lane, far below 2^32; the counting walks
     // keep (balanced, classified) per lane
@@ -814,12 +846,13 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
 
 // Work-group item: chunk `chunk` (caph entries) of a long source row, one shared table,
 // target rows split round-robin over the waves. Enumeration slots are per wave.
-template <int MODE, bool shorter, class G>
+template <int MODE, int PV, class G>
 __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict__ o_off,
                                 const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                                 const int32_t* __restrict__ len, const uint2* __restrict__ rinfo,
                                 const int32_t* __restrict__ perm, int64_t item, int64_t hq,
                                 BlockTab<G>& B, HistLds* H, WalkLaneState& st) {
+    constexpr bool shorter = (PV & 1) != 0;
     constexpr int WOFF = 4 << G::LGH;
     const int lane = utri_lane();
     const int wib = threadIdx.x / UTRI_WAVE;
@@ -846,7 +879,7 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     const int64_t slot = wp.lb + NW_MAX * hq + wib;
     int64_t run_b = 0, run_u = 0;
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[slot]; run_u = wp.off_u[slot]; }
-    walk_partners<MODE, shorter, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
+    walk_partners<MODE, PV, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
                                        wib, G::NW, H, st, run_b, run_u);
     // an item counts at most its candidates per lane, far below 2^32; the counting walks
     // keep (balanced, classified) per lane
@@ -907,7 +940,7 @@ __device__ void walk_flush(const WalkParams& wp, HistLds* H, WalkLaneState& st) 
 // items one per wave. Heaviest rows (highest ids) go first in both lists; work queues:
 // qctr[0] hands out heavy items to work-groups, qctr[1] light items to waves in groups of
 // four.
-template <int MODE, bool shorter, class G>
+template <int MODE, int PV, class G>
 __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_off,
                             const int32_t* __restrict__ o_adj, const double* __restrict__ o_d,
                             const int32_t* __restrict__ len, const uint2* __restrict__ rinfo,
@@ -923,7 +956,7 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         __syncthreads();
         if (q >= nh) break;
         const int64_t hq = nh - 1 - q;
-        walk_item_block<MODE, shorter, G>(wp, o_off, o_adj, o_d, len, rinfo, perm,
+        walk_item_block<MODE, PV, G>(wp, o_off, o_adj, o_d, len, rinfo, perm,
                                           items[wp.lb + hq], hq, S.block, H, st);
     }
     __syncthreads();  // the work-group table is no longer read; the wave tables reuse it
@@ -936,7 +969,7 @@ __device__ void walk_phases(const WalkParams& wp, const int64_t* __restrict__ o_
         const int64_t end = base + QGROUP < nl ? base + QGROUP : nl;
         for (int64_t q = base; q < end; q++) {
             const int64_t it = nl - 1 - q;
-            walk_item_wave<MODE, shorter, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items[it],
+            walk_item_wave<MODE, PV, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items[it],
                                              it, S.wave[wib], H, st);
         }
     }
@@ -958,7 +991,9 @@ struct WalkGeom<WALK_SIGN> {
     static_assert(2 * (1 << G::LGH) >= UTRI_SIGN_WALK_CHUNK, "chunks fit the table");
 };
 
-template <int MODE>
+// L3: the kernel of the Lemma-3 queries (its cut's code is compiled only here, so the
+// other kernels keep their registers).
+template <int MODE, bool L3>
 __global__ void __launch_bounds__(WalkGeom<MODE>::G::TPBW, WalkGeom<MODE>::MIN_WAVES) k_walk(WalkParams wp,
                                                           const int64_t* __restrict__ o_off,
                                                           const int32_t* __restrict__ o_adj,
@@ -979,12 +1014,13 @@ __global__ void __launch_bounds__(WalkGeom<MODE>::G::TPBW, WalkGeom<MODE>::MIN_W
     }
     WalkLaneState st;
     // both partner sources as their own code (the choice is uniform over the launch)
+    constexpr int PL = L3 ? 2 : 0;
+    const int64_t nl = n_items_dev[0], nh = n_items_dev[1];
     if (stream_shorter<MODE>(wp, n_items_dev))
-        walk_phases<MODE, true, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items, n_items_dev[0],
-                                   n_items_dev[1], S, H, st);
+        walk_phases<MODE, PL | 1, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items, nl, nh, S, H,
+                                     st);
     else
-        walk_phases<MODE, false, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items,
-                                    n_items_dev[0], n_items_dev[1], S, H, st);
+        walk_phases<MODE, PL, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items, nl, nh, S, H, st);
     walk_flush<MODE>(wp, H, st);
 }
 
@@ -1018,12 +1054,14 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
     else thresh_stage(sp.cvals, sp.nt);
     WalkLaneState st;
     if (wp.acc != nullptr) {
+        // (the batch walk counts with Lemma 2 only)
+        const int64_t nl = n_items_dev[0], nh = n_items_dev[1];
         if (stream_shorter<WALK_HIST>(wp, n_items_dev))
-            walk_phases<WALK_HIST, true, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items,
-                                            n_items_dev[0], n_items_dev[1], S.walk, H, st);
+            walk_phases<WALK_HIST, 1, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items, nl, nh,
+                                         S.walk, H, st);
         else
-            walk_phases<WALK_HIST, false, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items,
-                                             n_items_dev[0], n_items_dev[1], S.walk, H, st);
+            walk_phases<WALK_HIST, 0, G>(wp, o_off, o_adj, o_d, len, rinfo, perm, items, nl, nh,
+                                         S.walk, H, st);
         walk_flush<WALK_HIST>(wp, H, st);
     }
     __syncthreads();  // the walk's tables are no longer read; the sampler's reuse them
@@ -1032,9 +1070,8 @@ __global__ void __launch_bounds__(TPB) k_batch(WalkParams wp, const int64_t* __r
 
 }  // namespace
 
-int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int64_t** items,
+int utri_walk_prepare(utri_graph* g, double c_rows, int lemma3, hipStream_t s, int64_t** items,
                       int64_t** n_items_dev, int32_t** len) {
-    (void)cap;
     const int64_t n = g->n;
     const int64_t lb = light_bound(g), hb = heavy_bound(g);
     void *plen, *pcnt, *poff, *pitems, *pn, *pri;
@@ -1063,7 +1100,7 @@ int utri_walk_prepare(utri_graph* g, double c_rows, int cap, hipStream_t s, int6
     hipLaunchKernelGGL(k_rowlen, dim3(blocks_for(n)), dim3(TPB), 0, s, g->o_off, g->o_d, g->s_off,
                        g->s_d, n, c_rows, (int32_t*)plen, slen, lcnt, hcnt,
                        (unsigned long long*)pn + 4, (uint2*)pri, g->walk_tune.cap,
-                       g->walk_tune.caph, g->walk_tune.pr);
+                       g->walk_tune.caph, g->walk_tune.pr, lemma3);
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_scan_i32(g, lcnt, loff, n, (int64_t*)pn, s));
     UTRI_TRY(utri_scan_i32(g, hcnt, hoff, n, (int64_t*)pn + 1, s));
@@ -1140,13 +1177,26 @@ static int blocks_per_cu(utri_graph* g, K kernel, int tpb) {
     return nb;
 }
 
+template <int MODE, bool L3>
+static void launch_walk_k(utri_graph* g, const WalkParams& wp, const int32_t* len,
+                          const int64_t* items, const int64_t* n_items_dev, hipStream_t s) {
+    const int tpb = WalkGeom<MODE>::G::TPBW;
+    const int blocks = g->num_cu * blocks_per_cu(g, k_walk<MODE, L3>, tpb);
+    hipLaunchKernelGGL((k_walk<MODE, L3>), dim3(blocks), dim3(tpb), 0, s, wp, g->o_off, g->o_adj,
+                       g->o_d, len, (const uint2*)g->rinfo_cur, g->perm, items, n_items_dev);
+}
+
+// The Lemma-3 cut runs in the threshold walks of PRUNED_L3 queries on graphs with row codes
+// (at c = 0 it cuts nothing).
 template <int MODE>
 static void launch_walk(utri_graph* g, const WalkParams& wp, const int32_t* len,
                         const int64_t* items, const int64_t* n_items_dev, hipStream_t s) {
-    const int tpb = WalkGeom<MODE>::G::TPBW;
-    const int blocks = g->num_cu * blocks_per_cu(g, k_walk<MODE>, tpb);
-    hipLaunchKernelGGL(k_walk<MODE>, dim3(blocks), dim3(tpb), 0, s, wp, g->o_off, g->o_adj,
-                       g->o_d, len, (const uint2*)g->rinfo_cur, g->perm, items, n_items_dev);
+    constexpr bool kL3 = MODE == WALK_COUNT || MODE == WALK_HIST || MODE == WALK_ENUM_COUNT ||
+                         MODE == WALK_ENUM_FILL || MODE == WALK_STATS;
+    if (kL3 && wp.lemma3 && wp.mb > 0 && wp.c > 0.0)
+        launch_walk_k<MODE, kL3>(g, wp, len, items, n_items_dev, s);
+    else
+        launch_walk_k<MODE, false>(g, wp, len, items, n_items_dev, s);
 }
 
 int utri_walk_launch(utri_graph* g, int mode, const WalkParams& wp_in, const int64_t* items,
