@@ -640,9 +640,10 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
 
 // Stream the kept target row [ovs, ovs + lvs) of v, UNR strips of loads in flight. q3 > 0
 // (a row the Lemma-3 cut may shorten, see load_partners) stops the stream after the first
-// batch whose last entry has code q with q + 1 <= q3: that entry, and every later one (the
-// row is in |d| order), fails the cut, and the triangles of the entries that fail it are
-// unclassifiable, streamed or not.
+// batch of strips whose last entry has code q with q + 1 <= q3: that entry, and every later
+// one (the row is in |d| order), fails the cut, and the triangles of the entries that fail
+// it are unclassifiable, streamed or not. (Checking after every strip instead cuts more but
+// was slower on R-MAT s23.)
 template <int MODE, int UNR, int WOFF, bool L3>
 __device__ __forceinline__ void stream_row(const WalkParams& wp, const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, const TabRef& R,
@@ -660,8 +661,7 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const double* _
                                       run_b, run_u);
         if (L3 && q3 > 0 && j0 + UNR * UTRI_WAVE < lvs) {
             const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)pw[UNR - 1], UTRI_WAVE - 1);
-            const uint32_t qc = (wl >> wp.idbits) & ((1u << wp.mb) - 1u);
-            if ((int)qc + 1 <= q3) {
+            if ((int)((wl >> wp.idbits) & ((1u << wp.mb) - 1u)) + 1 <= q3) {
                 covered = j0 + UNR * UTRI_WAVE;
                 break;
             }

@@ -94,6 +94,42 @@ def test_walk_orders_match_oracle(order):
         utri.utri_set_walk_order(g.handle, 3)
 
 
+@pytest.mark.parametrize("mb", [0, 3, 8, 15])
+def test_lemma3_cut_shortens_rows_and_keeps_results(monkeypatch, mb):
+    """The Lemma-3 walk stops a marked row at the first batch of strips whose last entry's
+    code fails the cut: on R-MAT 16, with one strip per batch, it streams fewer ids than
+    the Lemma-2 walk once the codes are fine enough to resolve the cut (8 bits and up), and
+    counts and enumerations stay the oracle's at every code width. Without codes (mb = 0)
+    no row is cut."""
+    monkeypatch.setenv("UTRI_CODE_MB", str(mb))
+    n, lo, hi = inputs.rmat_graph(16, seed=7)
+    p = inputs.draw_p(lo.shape[0], "uniform", 9)
+    og = oracle.load(n, lo, hi, p)
+    g = gpu_graph(n, lo, hi, p)
+    g.set_tuning(walk_unroll=1)  # batches of one strip: the cut is checked after every strip
+    ts = [0.6, 0.75, 0.9]
+    want = og.count_multi(ts)
+    tot2 = tot3 = 0
+    for j, t in enumerate(ts):
+        say("lemma3 cut", mb, t)
+        for order in (utri.UTRI_ORDER_PLAIN, utri.UTRI_ORDER_SHORTER):
+            utri.utri_set_walk_order(g.handle, order)
+            assert g.count(t, utri.UTRI_PRUNED_L3) == tuple(want[j]), (mb, t, order)
+            s2 = utri.utri_walk_stats(g.handle, t, utri.UTRI_PRUNED)
+            s3 = utri.utri_walk_stats(g.handle, t, utri.UTRI_PRUNED_L3)
+            assert s3["candidates"] <= s2["candidates"] and s3["streamed"] <= s2["streamed"]
+            if mb == 0:
+                assert s3["streamed"] == s2["streamed"]
+            tot2 += s2["streamed"]
+            tot3 += s3["streamed"]
+        ob, ou = og.enumerate(t)
+        b, u = g.enumerate(t, utri.UTRI_PRUNED_L3)
+        assert np.array_equal(b.cpu().numpy(), ob) and np.array_equal(u.cpu().numpy(), ou)
+    if mb >= 8:
+        # rows longer than one strip are cut where the codes resolve the bound
+        assert tot3 < tot2, (mb, tot2, tot3)
+
+
 def test_count_which_selector():
     name, n, lo, hi = CASES[4]
     p = inputs.draw_p(lo.shape[0], "uniform", 1)
@@ -651,8 +687,9 @@ def test_narrow_codes_match_oracle(monkeypatch, mb):
                 assert np.array_equal(g.count_batch(ts), want)
             for t in (0.5625, 0.75, 0.9375):
                 ob, ou = og.enumerate(t)
-                b, u = g.enumerate(t)
-                assert np.array_equal(b.cpu().numpy(), ob) and np.array_equal(u.cpu().numpy(), ou)
+                for method in (utri.UTRI_PRUNED, utri.UTRI_PRUNED_L3):
+                    b, u = g.enumerate(t, method)
+                    assert np.array_equal(b.cpu().numpy(), ob) and np.array_equal(u.cpu().numpy(), ou)
             ex, es = g.batch(ts, 300, 4, 5, use_graph=False)
             assert np.array_equal(ex.cpu().numpy(), want)
             assert np.array_equal(es.cpu().numpy(), og.sample(ts, 300, 4, 5)[0])
