@@ -142,8 +142,13 @@ int utri_count_batch(utri_graph* g, const double* t, int nt, int method, int64_t
  * original vertex ids, each triple sorted ascending. out_counts (host int64 [2]) gets
  * the full list sizes. sorted = 1 sorts each list lexicographically; sorted = 0 leaves
  * it in a deterministic walk order. A class not selected by `which` is neither
- * written nor counted. If a list exceeds its capacity nothing is written for it and
- * UTRI_E_CAPACITY is returned with the sizes filled in, so the caller can retry.
+ * written nor counted. The call counts first (one walk) and then fills (a second). If a
+ * list exceeds its capacity nothing is written and UTRI_E_CAPACITY is returned with the
+ * sizes filled in, so the caller can retry: the handle then keeps the per-item counts of
+ * that query, and the next utri_enumerate on it with the same t, method and which, while
+ * the graph's P+, walk order and tuning are unchanged, fills from them without counting
+ * again (once; any other outcome forgets them). Probing with capacities 0 and retrying
+ * at the reported sizes therefore costs one counting walk and one fill.
  * Sorting a list of 2^32 triangles or more returns UTRI_E_RANGE (the unsorted list is
  * written).
  * Waits for the stream.

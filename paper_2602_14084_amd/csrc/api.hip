@@ -520,23 +520,48 @@ int utri_enumerate(utri_graph* g, double t, int method, int which, int32_t* bal,
     int64_t* off_b = (int64_t*)po;
     int64_t* off_u = off_b + bound;
     int64_t* tot = (int64_t*)ptot;
-    UTRI_TRY(utri_fill_u64(pc, 0, 2 * bound, s));
-    UTRI_TRY(utri_fill_u64(ptot, 0, 4, s));
-    WalkParams wp = base_params(method, c);
-    wp.cnt_b = cnt_b;
-    wp.cnt_u = cnt_u;
-    wp.which = which;
-    UTRI_TRY(utri_walk_launch(g, WALK_ENUM_COUNT, wp, items, nitems, len, 0, s));
-    UTRI_TRY(utri_scan_i64(g, cnt_b, off_b, bound, tot, s));
-    UTRI_TRY(utri_scan_i64(g, cnt_u, off_u, bound, tot + 1, s));
-    int64_t h[2] = {0, 0};
-    UTRI_HIP_TRY(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
-    UTRI_HIP_TRY(hipStreamSynchronize(s));
-    const int64_t nb = (which & UTRI_BAL) ? h[0] : 0;
-    const int64_t nu = (which & UTRI_UNBAL) ? h[1] : 0;
+    // the counts a call that returned UTRI_E_CAPACITY left for this same query, if any;
+    // they are used once
+    EnumTicket& tk = g->enum_ticket;
+    const bool reuse = tk.valid && tk.c == c && tk.method == method && tk.which == which &&
+                       tk.walk_order == g->walk_order && tk.walk_tune == g->walk_tune &&
+                       tk.scr_gen == g->scr_gen && tk.rows_gen == g->rows_gen;
+    tk.valid = false;
+    int64_t nb, nu;
+    if (reuse) {
+        nb = tk.nb;
+        nu = tk.nu;
+    } else {
+        UTRI_TRY(utri_fill_u64(pc, 0, 2 * bound, s));
+        UTRI_TRY(utri_fill_u64(ptot, 0, 4, s));
+        WalkParams wp = base_params(method, c);
+        wp.cnt_b = cnt_b;
+        wp.cnt_u = cnt_u;
+        wp.which = which;
+        UTRI_TRY(utri_walk_launch(g, WALK_ENUM_COUNT, wp, items, nitems, len, 0, s));
+        UTRI_TRY(utri_scan_i64(g, cnt_b, off_b, bound, tot, s));
+        UTRI_TRY(utri_scan_i64(g, cnt_u, off_u, bound, tot + 1, s));
+        int64_t h[2] = {0, 0};
+        UTRI_HIP_TRY(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+        UTRI_HIP_TRY(hipStreamSynchronize(s));
+        nb = (which & UTRI_BAL) ? h[0] : 0;
+        nu = (which & UTRI_UNBAL) ? h[1] : 0;
+    }
     out_counts[0] = nb;
     out_counts[1] = nu;
-    if (nb > cap_b || nu > cap_u) return UTRI_E_CAPACITY;
+    if (nb > cap_b || nu > cap_u) {
+        tk.valid = true;
+        tk.c = c;
+        tk.method = method;
+        tk.which = which;
+        tk.walk_order = g->walk_order;
+        tk.walk_tune = g->walk_tune;
+        tk.scr_gen = g->scr_gen;
+        tk.rows_gen = g->rows_gen;
+        tk.nb = nb;
+        tk.nu = nu;
+        return UTRI_E_CAPACITY;
+    }
     if ((nb > 0 && !bal) || (nu > 0 && !unbal)) return UTRI_E_INVALID;
     if (nb == 0 && nu == 0) return UTRI_OK;
     WalkParams wf = base_params(method, c);

@@ -384,6 +384,7 @@ int utri_exclusive_scan_i32_to_i64(utri_graph* g, const int32_t* in, int64_t* ou
 // Absolute Edge Order, oriented rows, hash tables. Used at load and after set_p.
 int utri_build_rows(utri_graph* g, hipStream_t s) {
     const int64_t n = g->n, m = g->m, cnt = 2 * m;
+    g->rows_gen++;
     if (cnt == 0) {
         UTRI_HIP_TRY(hipMemsetAsync(g->s_off, 0, sizeof(int64_t) * (n + 1), s));
         UTRI_HIP_TRY(hipMemsetAsync(g->o_off, 0, sizeof(int64_t) * (n + 1), s));

@@ -167,6 +167,18 @@ struct UtriBatchGraph {
     WalkTune walk_tune;
 };
 
+// Per-item counts of an enumeration (in SCR_ICNT2, offsets in SCR_IOFF2) that a
+// utri_enumerate call left behind when it returned UTRI_E_CAPACITY, with everything they
+// depend on; the next call of the same query with enough capacity fills from them once.
+struct EnumTicket {
+    bool valid = false;
+    double c = 0.0;
+    int method = 0, which = 0, walk_order = 0;
+    WalkTune walk_tune;
+    uint64_t scr_gen = 0, rows_gen = 0;
+    int64_t nb = 0, nu = 0;
+};
+
 struct utri_graph {
     int device = 0;
     int num_cu = 256;
@@ -207,6 +219,8 @@ struct utri_graph {
     void* scr[SCR_COUNT] = {};
     size_t scr_bytes[SCR_COUNT] = {};
     uint64_t scr_gen = 0;  // bumped whenever a scratch buffer is reallocated
+    uint64_t rows_gen = 0; // bumped whenever the rows (and their d) are rebuilt
+    EnumTicket enum_ticket;
     // No-allocation mode (set for the duration of one call): scratch slots are carved from
     // this caller-owned device arena instead of hipMalloc; a request that does not fit is
     // UTRI_E_CAPACITY.

@@ -360,7 +360,7 @@ struct WalkLaneState {
     uint32_t bs[SIGN_K] = {};      // SIGN: bit planes of this lane's 32 world counters
     uint32_t npass = 0;            // SIGN: additions since the last flush (wave-uniform)
     int qn = 0;                    // SIGN: queued triangles (wave-uniform)
-    int dn = 0;                    // COUNT / ENUM_COUNT: deferred hits queued (wave-uniform)
+    int dn = 0;                    // COUNT / ENUM_*: hits queued (wave-uniform)
 };
 
 // SIGN: per-wave queue of triangles as their three edge ids
@@ -483,6 +483,63 @@ __device__ __forceinline__ void defer_drain(const WalkParams& wp, const double* 
     utri_wave_sync();
 }
 
+// The fill walk queues its hits in the same per-wave queue, in probe order, as (id of w |
+// its class) or, for a hit the codes leave undecided, (position of d_vw, class 3), and
+// writes them in batches: a wave waits for the permutation loads of its triangles' third
+// vertex (and the d loads of the undecided ones) once per batch instead of once per
+// strip. Written in queue order, the lists keep the order in which the strips were
+// probed. Queue words: vw = id of w or position of d_vw; ps = staged position | partner
+// slot << 15 | class << 21 (1 balanced, 2 unbalanced, 3 undecided).
+constexpr uint32_t FQ_BAL = 1u, FQ_UNBAL = 2u, FQ_UND = 3u;
+
+// pv_lanes / duv_lanes: original id of y and d_xy of the batch's partners on their lanes.
+__device__ __forceinline__ void fill_drain(const WalkParams& wp, const double* __restrict__ o_d,
+                                           const int32_t* __restrict__ perm, int64_t src_base,
+                                           int32_t pu, int32_t pv_lanes, double duv_lanes,
+                                           WalkLaneState& st, int64_t& run_b, int64_t& run_u) {
+    DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+    utri_wave_sync();
+    for (int e0 = 0; e0 < st.dn; e0 += UTRI_WAVE) {
+        const int e = e0 + utri_lane();
+        const bool live = e < st.dn;
+        const uint32_t ps = live ? Q.ps[e] : 0u;
+        const uint32_t vw = live ? Q.vw[e] : 0u;
+        const int si = (int)((ps >> 15) & 63u);
+        const uint32_t cls = ps >> 21;
+        const double duv = __shfl(duv_lanes, si, UTRI_WAVE);
+        const int32_t pv = __shfl(pv_lanes, si, UTRI_WAVE);
+        bool is_b = cls == FQ_BAL, is_u = cls == FQ_UNBAL;
+        uint32_t w = vw;
+        if (cls == FQ_UND) {
+            // the exact FP64 rule reads d_uw and d_vw
+            w = (uint32_t)wp.o_adj[vw] & wp.idmask;
+            const double s = utri_tri_s(duv, o_d[src_base + (ps & W_POS)], o_d[vw]);
+            is_b = s <= -wp.c && (wp.which & UTRI_BAL);
+            is_u = s > wp.c && (wp.which & UTRI_UNBAL);
+        }
+        const uint64_t mb_ = __ballot(is_b);
+        const uint64_t mu_ = __ballot(is_u);
+        if (is_b || is_u) {
+            int32_t a = pu, b = pv, c = perm[w], t;
+            if (b < a) { t = a; a = b; b = t; }
+            if (c < b) { t = b; b = c; c = t; }
+            if (b < a) { t = a; a = b; b = t; }
+            const uint64_t lt = __lanemask_lt();
+            int32_t* dst;
+            int64_t slot;
+            if (is_b) { dst = wp.out_bal; slot = run_b + __popcll(mb_ & lt); }
+            else      { dst = wp.out_unbal; slot = run_u + __popcll(mu_ & lt); }
+            dst[3 * slot] = a;
+            dst[3 * slot + 1] = b;
+            dst[3 * slot + 2] = c;
+        }
+        run_b += __popcll(mb_);
+        run_u += __popcll(mu_);
+    }
+    st.dn = 0;
+    utri_wave_sync();
+}
+
 // Stream the kept target row [ovs, ovs + lvs) of v, probing every entry in the table.
 // Row entries are packed words (id in the low idbits bits, mb-bit d code above, sign(d)
 // in bit 31); table words carry the staged entry's code and position. si: the partner's
@@ -515,8 +572,8 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
                                              const int32_t* __restrict__ perm, const TabRef& R,
                                              const uint32_t (&pw)[UNR], int j0, int64_t ovs,
                                              int lvs, double duvs, int32_t pv, const CodeRow& cr,
-                                             int si, HistLds* H, WalkLaneState& st,
-                                             int64_t& run_b, int64_t& run_u) {
+                                             int si, double duv_lanes, HistLds* H,
+                                             WalkLaneState& st, int64_t& run_b, int64_t& run_u) {
     const int lane = utri_lane();
     constexpr bool kCoded = UTRI_WALK_CODES && (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT ||
                                                 MODE == WALK_ENUM_FILL);
@@ -563,47 +620,33 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
                     }
                 }
             } else if (MODE == WALK_ENUM_FILL) {
-                bool is_b = false, is_u = false;
-                bool und = found;
+                // pv: the partners' original ids on their lanes (see fill_drain)
+                uint32_t cls = found ? FQ_UND : 0u;
                 if (kCoded) {
                     const uint32_t qb = (r >> 16) & ((1u << QB) - 1u);
                     const uint32_t qc = (pw[k] >> wp.idbits) & qm;
                     const uint32_t p0 = __umul24(qb, qc);
                     const uint32_t t1 = p0 + qb + qc;  // (qb + 1)(qc + 1) - 1
-                    const bool cls = p0 >= cr.khi;
-                    const bool nei = t1 < cr.klo;
                     const bool neg = (int32_t)(r ^ pw[k] ^ cr.rsign) < 0;
-                    is_b = found && cls && neg;
-                    is_u = found && cls && !neg;
-                    und = found && !cls && !nei;
+                    if (p0 >= cr.khi)
+                        cls = !found ? 0u : neg ? ((wp.which & UTRI_BAL) ? FQ_BAL : 0u)
+                                                : ((wp.which & UTRI_UNBAL) ? FQ_UNBAL : 0u);
+                    else if (t1 < cr.klo)
+                        cls = 0u;
                 }
-                {
-                    if (und) {
-                        // the exact FP64 rule reads d_uw and d_vw
-                        const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
-                        is_b = s <= -wp.c;
-                        is_u = s > wp.c;
+                const uint64_t qm_ = __ballot(cls != 0u);
+                if (qm_) {
+                    const int nq = __popcll(qm_);
+                    if (st.dn + nq > DQ_CAP)
+                        fill_drain(wp, o_d, perm, R.src_base, R.pu, pv, duv_lanes, st, run_b,
+                                   run_u);
+                    if (cls) {
+                        DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+                        const int slot = st.dn + __popcll(qm_ & __lanemask_lt());
+                        Q.vw[slot] = cls == FQ_UND ? (uint32_t)(ovs + j) : w;
+                        Q.ps[slot] = (r & W_POS) | ((uint32_t)si << 15) | (cls << 21);
                     }
-                    is_b = is_b && (wp.which & UTRI_BAL);
-                    is_u = is_u && (wp.which & UTRI_UNBAL);
-                    const uint64_t mb_ = __ballot(is_b);
-                    const uint64_t mu_ = __ballot(is_u);
-                    if (is_b || is_u) {
-                        int32_t a = R.pu, b = pv, c = perm[w], t;
-                        if (b < a) { t = a; a = b; b = t; }
-                        if (c < b) { t = b; b = c; c = t; }
-                        if (b < a) { t = a; a = b; b = t; }
-                        const uint64_t lt = __lanemask_lt();
-                        int32_t* dst;
-                        int64_t slot;
-                        if (is_b) { dst = wp.out_bal; slot = run_b + __popcll(mb_ & lt); }
-                        else      { dst = wp.out_unbal; slot = run_u + __popcll(mu_ & lt); }
-                        dst[3 * slot] = a;
-                        dst[3 * slot + 1] = b;
-                        dst[3 * slot + 2] = c;
-                    }
-                    run_b += __popcll(mb_);
-                    run_u += __popcll(mu_);
+                    st.dn += nq;
                 }
             } else if (MODE == WALK_STATS) {
                 if (found) st.tri++;
@@ -651,14 +694,13 @@ __device__ __forceinline__ void stream_row(const WalkParams& wp, const double* _
                                            const CodeRow& cr, int si, double duv_lanes, int q3,
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
-    (void)duv_lanes;
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(wp, ovs, lvs);
     int covered = lvs;
     for (int j0 = 0; j0 < lvs; j0 += UNR * UTRI_WAVE) {
         uint32_t pw[UNR];
         load_strips<UNR>(rs, j0, pw);  // all UNR loads are issued before any probe
-        probe_strips<MODE, UNR, WOFF>(wp, o_d, perm, R, pw, j0, ovs, lvs, duvs, pv, cr, si, H, st,
-                                      run_b, run_u);
+        probe_strips<MODE, UNR, WOFF>(wp, o_d, perm, R, pw, j0, ovs, lvs, duvs, pv, cr, si,
+                                      duv_lanes, H, st, run_b, run_u);
         if (L3 && q3 > 0 && j0 + UNR * UTRI_WAVE < lvs) {
             const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)pw[UNR - 1], UTRI_WAVE - 1);
             if ((int)((wl >> wp.idbits) & ((1u << wp.mb) - 1u)) + 1 <= q3) {
@@ -681,9 +723,9 @@ __device__ __forceinline__ void stream_any(const WalkParams& wp, const double* _
                                            HistLds* H, WalkLaneState& st, int64_t& run_b,
                                            int64_t& run_u) {
 #if UTRI_WALK_UNR_MAX >= 8
-    // the sign-world walk keeps its counter planes in registers: eight loads ahead would
-    // spill them
-    if (MODE != WALK_SIGN && lvs > 4 * UTRI_WAVE && wp.tune.unr >= 8)
+    // the sign-world walk keeps its counter planes in registers, and the fill walk its
+    // queue drain's: eight loads ahead would spill them
+    if (MODE != WALK_SIGN && MODE != WALK_ENUM_FILL && lvs > 4 * UTRI_WAVE && wp.tune.unr >= 8)
         stream_row<MODE, 8, WOFF, L3>(wp, o_d, perm, R, ovs, lvs, duvs, pv, cr, si, duv_lanes, q3, H, st,
                                   run_b, run_u);
     else
@@ -778,13 +820,15 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
                                      dmax_chunk, v, ov, lv, duv, euv, cr);
         // this wave's partners in the batch: i0 + part + nparts * si < np
         const int nv = min(UTRI_WAVE, (np - i0 - part + nparts - 1) / nparts);
+        // fill: the partners' original ids on their lanes (fill_drain reads them by slot)
+        const int32_t pvl = (MODE == WALK_ENUM_FILL && lv != 0) ? perm[v] : 0;
         // lane by lane (a loop over the set bits of a ballot made the sign-world walk slower
         // and the others no faster)
         for (int si = 0; si < nv; si++) {
             const int lvm = bcast_i32(lv, si);
             const int lvs = lvm & 0xFFFF;
             if (lvs == 0) continue;
-            const int32_t pv = (MODE == WALK_ENUM_FILL) ? perm[bcast_i32(v, si)]
+            const int32_t pv = (MODE == WALK_ENUM_FILL) ? pvl
                                : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
                               (uint32_t)bcast_i32((int)cr.klo, si),
@@ -798,6 +842,8 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
         // deferred hits use this batch's d_xy
         if ((MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) && st.dn > 0)
             defer_drain(wp, o_d, R.src_base, duv, st);
+        if (MODE == WALK_ENUM_FILL && st.dn > 0)
+            fill_drain(wp, o_d, perm, R.src_base, R.pu, pvl, duv, st, run_b, run_u);
     }
 }
 

@@ -203,11 +203,12 @@ def utri_count_batch(h, ts, method=UTRI_PRUNED, stream=None):
 
 def utri_enumerate(h, t, method=UTRI_PRUNED, which=UTRI_BOTH, sorted=True, cap=None,
                    stream=None):
-    """(balanced, unbalanced) CUDA int32 tensors of shape [k, 3] (original vertex ids)."""
+    """(balanced, unbalanced) CUDA int32 tensors of shape [k, 3] (original vertex ids).
+
+    Without `cap` the library is probed with capacities 0 first: it counts, reports the
+    sizes, and the call at those sizes fills from the counts it kept."""
     torch = _torch()
-    if cap is None:
-        cap = utri_count(h, t, method, which, stream)
-    cb, cu = int(cap[0]), int(cap[1])
+    cb, cu = (0, 0) if cap is None else (int(cap[0]), int(cap[1]))
     bal = torch.empty((max(cb, 1), 3), dtype=torch.int32, device="cuda")
     unb = torch.empty((max(cu, 1), 3), dtype=torch.int32, device="cuda")
     counts = (C.c_int64 * 2)()
@@ -215,6 +216,8 @@ def utri_enumerate(h, t, method=UTRI_PRUNED, which=UTRI_BOTH, sorted=True, cap=N
                               C.c_void_p(unb.data_ptr()), cu, counts, 1 if sorted else 0,
                               _stream(stream))
     if rc == UTRI_E_CAPACITY:
+        if cap is not None and counts[0] <= cb and counts[1] <= cu:
+            _check(rc, "utri_enumerate")
         return utri_enumerate(h, t, method, which, sorted, (counts[0], counts[1]), stream)
     _check(rc, "utri_enumerate")
     return bal[:counts[0]], unb[:counts[1]]

@@ -209,6 +209,31 @@ def test_enumerate_which_and_capacity():
     # the binding grows its buffers and retries
     bal, unb = utri.utri_enumerate(g.handle, 0.6, cap=(cb, cu))
     assert np.array_equal(bal.cpu().numpy(), ob) and np.array_equal(unb.cpu().numpy(), ou)
+    # the counts a UTRI_E_CAPACITY return keeps serve only the same query on the same rows
+
+    def probe(t):
+        rc = utri.lib().utri_enumerate(g.handle, t, utri.UTRI_PRUNED, utri.UTRI_BOTH, None, 0,
+                                       None, 0, counts, 1,
+                                       C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == utri.UTRI_E_CAPACITY
+        return int(counts[0]), int(counts[1])
+
+    assert probe(0.6) == (ob.shape[0], ou.shape[0])
+    ob7, ou7 = og.enumerate(0.75)
+    bal, unb = utri.utri_enumerate(g.handle, 0.75, cap=(ob7.shape[0] + 3, ou7.shape[0] + 3))
+    assert np.array_equal(bal.cpu().numpy(), ob7) and np.array_equal(unb.cpu().numpy(), ou7)
+    assert probe(0.6) == (ob.shape[0], ou.shape[0])
+    p2 = inputs.draw_p(lo.shape[0], "uniform", 2)
+    og2 = oracle.load(n, lo, hi, p2)
+    ob2, ou2 = og2.enumerate(0.6)
+    g.set_p(torch.from_numpy(p2).cuda())
+    bal, unb = utri.utri_enumerate(g.handle, 0.6, cap=(ob2.shape[0] + 3, ou2.shape[0] + 3))
+    assert np.array_equal(bal.cpu().numpy(), ob2) and np.array_equal(unb.cpu().numpy(), ou2)
+    # a kept count is used once: a second call at capacity counts again
+    assert probe(0.6) == (ob2.shape[0], ou2.shape[0])
+    for _ in range(2):
+        bal, unb = utri.utri_enumerate(g.handle, 0.6, cap=(ob2.shape[0], ou2.shape[0]))
+        assert np.array_equal(bal.cpu().numpy(), ob2) and np.array_equal(unb.cpu().numpy(), ou2)
 
 
 def test_expected_matches_oracle_exactly():
