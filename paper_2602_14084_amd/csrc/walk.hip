@@ -178,20 +178,33 @@ __device__ __forceinline__ void tab_stage(uint32_t* key, const int32_t* __restri
 }
 
 // The word of id w, 0 if absent. Lanes past a streamed row's end probe w = 0, which only
-// matches empty slots, whose words are 0.
+// matches empty slots, whose words are 0. tab_bucket looks in one bucket (full: its last
+// slot is taken, so w may lie further on).
+template <int WOFF>
+__device__ __forceinline__ uint32_t tab_bucket(const uint32_t* key, uint32_t b, uint32_t w,
+                                               bool& full) {
+    const uint4 k = *reinterpret_cast<const uint4*>(key + 4 * b);
+    const uint4 d = *reinterpret_cast<const uint4*>(key + WOFF + 4 * b);
+    uint32_t r = (k.w == w) ? d.w : 0u;
+    r = (k.z == w) ? d.z : r;
+    r = (k.y == w) ? d.y : r;
+    r = (k.x == w) ? d.x : r;
+    full = k.w != 0u;
+    return r;
+}
+
 template <int WOFF>
 __device__ __forceinline__ uint32_t tab_find(const uint32_t* key, uint32_t bmask, uint32_t w) {
     uint32_t b = w & bmask;
-    uint32_t r;
-    for (;;) {
-        const uint4 k = *reinterpret_cast<const uint4*>(key + 4 * b);
-        const uint4 d = *reinterpret_cast<const uint4*>(key + WOFF + 4 * b);
-        r = (k.w == w) ? d.w : 0u;
-        r = (k.z == w) ? d.z : r;
-        r = (k.y == w) ? d.y : r;
-        r = (k.x == w) ? d.x : r;
-        if (r != 0u || k.w == 0u) break;
-        b = (b + 1) & bmask;
+    bool full;
+    uint32_t r = tab_bucket<WOFF>(key, b, w, full);
+    // a full bucket without w sends the lane on to the next one (rare: the tables hold at
+    // most half an entry per bucket)
+    if (__builtin_expect(r == 0u && full, 0)) {
+        do {
+            b = (b + 1) & bmask;
+            r = tab_bucket<WOFF>(key, b, w, full);
+        } while (r == 0u && full);
     }
     return r;
 }
@@ -483,25 +496,37 @@ __device__ __forceinline__ void defer_drain(const WalkParams& wp, const double* 
     utri_wave_sync();
 }
 
-// The fill walk queues its hits in the same per-wave queue, in probe order, as (id of w |
-// its class) or, for a hit the codes leave undecided, (position of d_vw, class 3), and
+// The fill walk queues its hits per wave, in probe order, as (id of w, its class) or,
+// for a hit the codes leave undecided, (position of d_vw, class 3), and
 // writes them in batches: a wave waits for the permutation loads of its triangles' third
 // vertex (and the d loads of the undecided ones) once per batch instead of once per
 // strip. Written in queue order, the lists keep the order in which the strips were
 // probed. Queue words: vw = id of w or position of d_vw; ps = staged position | partner
 // slot << 15 | class << 21 (1 balanced, 2 unbalanced, 3 undecided).
 constexpr uint32_t FQ_BAL = 1u, FQ_UNBAL = 2u, FQ_UND = 3u;
+// A full queue is drained 64 entries at a time (the rest move to the front), so every
+// batch but an item's last fills the wave. 120 entries keep the fill walk's work-group
+// within a quarter of the LDS.
+constexpr int FQ_CAP = 120;
+struct FillQueue {
+    uint32_t vw[FQ_CAP];
+    uint32_t ps[FQ_CAP];
+};
+__shared__ FillQueue fill_q[NW_MAX];
 
-// pv_lanes / duv_lanes: original id of y and d_xy of the batch's partners on their lanes.
+// pv_lanes / duv_lanes: original id of y and d_xy of the batch's partners on their lanes;
+// all: drain every entry (else the first 64 when there are that many).
 __device__ __forceinline__ void fill_drain(const WalkParams& wp, const double* __restrict__ o_d,
                                            const int32_t* __restrict__ perm, int64_t src_base,
                                            int32_t pu, int32_t pv_lanes, double duv_lanes,
-                                           WalkLaneState& st, int64_t& run_b, int64_t& run_u) {
-    DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+                                           WalkLaneState& st, int64_t& run_b, int64_t& run_u,
+                                           bool all) {
+    FillQueue& Q = fill_q[threadIdx.x / UTRI_WAVE];
     utri_wave_sync();
-    for (int e0 = 0; e0 < st.dn; e0 += UTRI_WAVE) {
+    const int take = (all || st.dn < UTRI_WAVE) ? st.dn : UTRI_WAVE;
+    for (int e0 = 0; e0 < take; e0 += UTRI_WAVE) {
         const int e = e0 + utri_lane();
-        const bool live = e < st.dn;
+        const bool live = e < take;
         const uint32_t ps = live ? Q.ps[e] : 0u;
         const uint32_t vw = live ? Q.vw[e] : 0u;
         const int si = (int)((ps >> 15) & 63u);
@@ -536,7 +561,16 @@ __device__ __forceinline__ void fill_drain(const WalkParams& wp, const double* _
         run_b += __popcll(mb_);
         run_u += __popcll(mu_);
     }
-    st.dn = 0;
+    // the entries left (at most FQ_CAP - 64) move to the front
+    const int rest = st.dn - take;
+    if (rest > 0) {
+        const int e = utri_lane();
+        uint32_t ps = 0u, vw = 0u;
+        if (e < rest) { ps = Q.ps[take + e]; vw = Q.vw[take + e]; }
+        utri_wave_sync();
+        if (e < rest) { Q.ps[e] = ps; Q.vw[e] = vw; }
+    }
+    st.dn = rest;
     utri_wave_sync();
 }
 
@@ -596,23 +630,26 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
                 const uint32_t qc = __builtin_amdgcn_ubfe(pw[k], wp.idbits, wp.mb);
                 const uint32_t p0 = __umul24(qb, qc);
                 const uint32_t t1 = p0 + qb + qc;  // (qb + 1)(qc + 1) - 1
+                // khi >= 1, so an absent w (r = 0, qb = 0) is never classified
                 const bool ccls = p0 >= cr.khi;
-                const uint32_t cls = (found && ccls) ? 1u : 0u;
-                st.nb32 += cls & ((r ^ pw[k] ^ cr.rsign) >> 31);
-                st.nu32 += cls;
+                const bool bal = ccls && (int32_t)(r ^ pw[k] ^ cr.rsign) < 0;
+                st.nb32 += bal ? 1u : 0u;
+                st.nu32 += ccls ? 1u : 0u;
                 const bool und = found && !ccls && t1 >= cr.klo;
-                const uint64_t um = __ballot(und);
+                const uint64_t um = __builtin_amdgcn_ballot_w64(und);
                 if (um) {
+                    // this lane's bit of the ballot (keeps und itself out of the branch)
+                    const bool mine = (um >> lane) & 1ull;
                     const int nq = __popcll(um);
                     if (st.dn + nq <= DQ_CAP) {
-                        if (und) {
+                        if (mine) {
                             DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
                             const int slot = st.dn + __popcll(um & __lanemask_lt());
                             Q.vw[slot] = (uint32_t)(ovs + j);
                             Q.ps[slot] = (r & W_POS) | ((uint32_t)si << 15);
                         }
                         st.dn += nq;
-                    } else if (und) {
+                    } else if (mine) {
                         const double s = utri_tri_s(duvs, o_d[R.src_base + (r & W_POS)], rowd[j]);
                         const uint32_t c = (s <= -wp.c || s > wp.c) ? 1u : 0u;
                         st.nb32 += (s <= -wp.c) ? 1u : 0u;
@@ -637,11 +674,11 @@ __device__ __forceinline__ void probe_strips(const WalkParams& wp, const double*
                 const uint64_t qm_ = __ballot(cls != 0u);
                 if (qm_) {
                     const int nq = __popcll(qm_);
-                    if (st.dn + nq > DQ_CAP)
+                    if (st.dn + nq > FQ_CAP)
                         fill_drain(wp, o_d, perm, R.src_base, R.pu, pv, duv_lanes, st, run_b,
-                                   run_u);
+                                   run_u, false);
                     if (cls) {
-                        DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+                        FillQueue& Q = fill_q[threadIdx.x / UTRI_WAVE];
                         const int slot = st.dn + __popcll(qm_ & __lanemask_lt());
                         Q.vw[slot] = cls == FQ_UND ? (uint32_t)(ovs + j) : w;
                         Q.ps[slot] = (r & W_POS) | ((uint32_t)si << 15) | (cls << 21);
@@ -843,7 +880,7 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
         if ((MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) && st.dn > 0)
             defer_drain(wp, o_d, R.src_base, duv, st);
         if (MODE == WALK_ENUM_FILL && st.dn > 0)
-            fill_drain(wp, o_d, perm, R.src_base, R.pu, pvl, duv, st, run_b, run_u);
+            fill_drain(wp, o_d, perm, R.src_base, R.pu, pvl, duv, st, run_b, run_u, true);
     }
 }
 
