@@ -250,7 +250,7 @@ __global__ void k_hsize(const int32_t* __restrict__ deg_new, int64_t n, int64_t*
 // home bucket on, that has one; slots therefore fill in order within a bucket.
 __global__ void k_hinsert(const int32_t* __restrict__ s_row, const int32_t* __restrict__ s_adj,
                           const double* __restrict__ s_d, const int64_t* __restrict__ h_off,
-                          int64_t cnt, uint32_t* __restrict__ hkey, double* __restrict__ hd) {
+                          int64_t cnt, uint32_t* __restrict__ htab) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
     const int32_t r = s_row[i];
@@ -264,10 +264,11 @@ __global__ void k_hinsert(const int32_t* __restrict__ s_row, const int32_t* __re
         const int64_t b0 = base + (int64_t)b * UTRI_HB;
         // claim the first slot seen empty; a lost race moves on to the next one
         int q = 0;
-        while (q < UTRI_HB && __atomic_load_n(&hkey[b0 + q], __ATOMIC_RELAXED) != 0xFFFFFFFFu) q++;
+        uint32_t* hkey = htab + utri_hkey_index(b0);
+        while (q < UTRI_HB && __atomic_load_n(&hkey[q], __ATOMIC_RELAXED) != 0xFFFFFFFFu) q++;
         for (; q < UTRI_HB; q++) {
-            if (atomicCAS(&hkey[b0 + q], 0xFFFFFFFFu, (uint32_t)key) == 0xFFFFFFFFu) {
-                hd[b0 + q] = s_d[i];
+            if (atomicCAS(&hkey[q], 0xFFFFFFFFu, (uint32_t)key) == 0xFFFFFFFFu) {
+                reinterpret_cast<double*>(htab)[utri_hd_index(b0 + q)] = s_d[i];
                 return;
             }
         }
@@ -451,9 +452,9 @@ int utri_build_rows(utri_graph* g, hipStream_t s) {
     UTRI_HIP_TRY(hipGetLastError());
     UTRI_TRY(utri_exclusive_scan_i64(g, hs, g->h_off, n, s));
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, g->h_off + n, g->h_total);
-    UTRI_TRY(utri_fill_u64(g->h_key, ~0ull, g->h_total / 2, s));  // h_total is a multiple of 8
+    UTRI_TRY(utri_fill_u64(g->h_tab, ~0ull, g->h_total * 2, s));  // 16 bytes per slot
     hipLaunchKernelGGL(k_hinsert, dim3(nb), dim3(TPB), 0, s, g->s_row, g->s_adj, g->s_d,
-                       g->h_off, cnt, g->h_key, g->h_d);
+                       g->h_off, cnt, g->h_tab);
     UTRI_HIP_TRY(hipGetLastError());
     // temporaries are freed at scope exit; hipFree waits for the device
     UTRI_HIP_TRY(hipStreamSynchronize(s));
@@ -463,7 +464,7 @@ int utri_build_rows(utri_graph* g, hipStream_t s) {
 static void free_graph(utri_graph* g) {
     if (!g) return;
     void* ptrs[] = {g->e_lo, g->e_hi, g->e_p, g->e_d, g->perm, g->inv, g->deg_new, g->s_off,
-                    g->s_adj, g->s_d, g->s_eid, g->s_row, g->h_off, g->h_key, g->h_d, g->o_off,
+                    g->s_adj, g->s_d, g->s_eid, g->s_row, g->h_off, g->h_tab, g->o_off,
                     g->o_adj, g->o_d, g->o_eid, g->d_flags};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -615,8 +616,7 @@ static int load_impl(const int64_t* src, const int64_t* dst, const double* p, in
         for (int64_t v = 0; v < n; v++) tot += utri_htable_slots(hdeg[v]);
         g->h_total = tot;
     }
-    UTRI_TRY(dev_alloc(&g->h_key, g->h_total));
-    UTRI_TRY(dev_alloc(&g->h_d, g->h_total));
+    UTRI_TRY(dev_alloc(&g->h_tab, g->h_total / UTRI_HB * UTRI_HB_WORDS));
     UTRI_TRY(utri_build_rows(g, s));
     // maximum out-degree
     if (n > 0) {

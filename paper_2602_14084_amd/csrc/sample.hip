@@ -166,9 +166,9 @@ __global__ void __launch_bounds__(TPB) k_edge_local(SampleGraph G, const double*
         const int lg = hbuckets_lg(G, y);
         for (int64_t j = lane; j < lx; j += UTRI_WAVE) {
             const int32_t w = G.s_adj[xoff + j];
-            const int64_t sl = sym_lookup(G.h_key, hoff, lg, w);
+            const int64_t sl = sym_lookup(G.h_tab, hoff, lg, w);
             if (sl >= 0) {
-                const double s = utri_tri_s(de, G.s_d[xoff + j], G.h_d[sl]);
+                const double s = utri_tri_s(de, G.s_d[xoff + j], sym_d(G.h_tab, sl));
                 bool bal;
                 const int bin = thresh_bin(s, bal);
                 if (bin > 0) atomicAdd(&hist[wib][bal ? 0 : 1][bin], 1ull);
@@ -248,9 +248,9 @@ __global__ void __launch_bounds__(TPB) k_vertex_local(SampleGraph G, const int32
             const int64_t hoff = G.h_off[y];
             const int lg = hbuckets_lg(G, y);
             for (int j = lane; j < lx; j += UTRI_WAVE) {
-                const int64_t sl = sym_lookup(G.h_key, hoff, lg, G.s_adj[xoff + j]);
+                const int64_t sl = sym_lookup(G.h_tab, hoff, lg, G.s_adj[xoff + j]);
                 if (sl >= 0) {
-                    const double s = utri_tri_s(de, G.s_d[xoff + j], G.h_d[sl]);
+                    const double s = utri_tri_s(de, G.s_d[xoff + j], sym_d(G.h_tab, sl));
                     bool bal;
                     const int bin = thresh_bin(s, bal);
                     if (bin > 0) atomicAdd(&hist[wib][bal ? 0 : 1][bin], 1ull);
@@ -278,12 +278,13 @@ __global__ void k_topk_keys(SampleGraph G, const int32_t* __restrict__ tri, int6
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int32_t a = G.inv[tri[3 * i]], b = G.inv[tri[3 * i + 1]], c = G.inv[tri[3 * i + 2]];
-    const int64_t ab = sym_lookup(G.h_key, G.h_off[a], hbuckets_lg(G, a), b);
-    const int64_t ac = sym_lookup(G.h_key, G.h_off[a], hbuckets_lg(G, a), c);
-    const int64_t bc = sym_lookup(G.h_key, G.h_off[b], hbuckets_lg(G, b), c);
+    const int64_t ab = sym_lookup(G.h_tab, G.h_off[a], hbuckets_lg(G, a), b);
+    const int64_t ac = sym_lookup(G.h_tab, G.h_off[a], hbuckets_lg(G, a), c);
+    const int64_t bc = sym_lookup(G.h_tab, G.h_off[b], hbuckets_lg(G, b), c);
     // the listed triples are triangles, so every lookup hits
-    const double s = utri_tri_s(ab >= 0 ? G.h_d[ab] : 0.0, ac >= 0 ? G.h_d[ac] : 0.0,
-                                bc >= 0 ? G.h_d[bc] : 0.0);
+    const double s = utri_tri_s(ab >= 0 ? sym_d(G.h_tab, ab) : 0.0,
+                                ac >= 0 ? sym_d(G.h_tab, ac) : 0.0,
+                                bc >= 0 ? sym_d(G.h_tab, bc) : 0.0);
     sv[i] = s;
     uint64_t u = (uint64_t)__double_as_longlong(s == 0.0 ? 0.0 : s);
     u = (u >> 63) ? ~u : (u | (1ull << 63));
@@ -340,7 +341,7 @@ int utri_sym_prepare(utri_graph* g, double c_rows, hipStream_t s, int32_t** slen
 
 static SampleGraph sample_graph(utri_graph* g) {
     return SampleGraph{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d,
-                       g->h_off, g->h_key, g->h_d};
+                       g->h_off, g->h_tab};
 }
 
 int utri_sample_prepare(utri_graph* g, SampleParams& sp, const int32_t* slen, int64_t t0,

@@ -10,11 +10,11 @@
 //       each row in Absolute Edge Order  s_d f64 [2m], s_eid int32 [2m]
 //       (|d| descending, then neighbour id ascending; Section 5), so the entries
 //       with |d| >= c of any row form a prefix.
-//   per-row bucketed hash tables        h_off int64 [n+1] (slots), h_key u32 [sum],
-//       h_d f64 [sum]: buckets of 8 slots (32 bytes of keys: neighbour id, ~0 = empty),
-//       and each slot's d of the edge to that neighbour; slots fill in order; size =
-//       pow2 >= max(3*deg, 8), a load factor of at most 1/3, so a lookup almost always
-//       reads one bucket.
+//   per-row bucketed hash tables        h_off int64 [n+1] (slots), h_tab u32 [4 * sum]:
+//       buckets of 8 slots, 128 bytes each: the keys (neighbour id, ~0 = empty; 32
+//       bytes), each slot's d of the edge to that neighbour (64 bytes), 32 bytes of
+//       padding; slots fill in order; size = pow2 >= max(3*deg, 8), a load factor of at
+//       most 1/3, so a lookup almost always reads one bucket.
 //   oriented rows u -> v (v > u)        o_off int64 [n+1], o_adj int32 [m],
 //       same Absolute Edge Order         o_d f64 [m], o_eid int32 [m]
 #pragma once
@@ -197,8 +197,7 @@ struct utri_graph {
     int32_t* s_row = nullptr;    // row of each symmetric entry
 
     int64_t* h_off = nullptr;
-    uint32_t* h_key = nullptr;
-    double* h_d = nullptr;
+    uint32_t* h_tab = nullptr;   // UTRI_HB_WORDS words per bucket (utri_hkey_index)
     int64_t h_total = 0;
 
     int64_t* o_off = nullptr;
@@ -317,6 +316,18 @@ __host__ __device__ inline int64_t utri_htable_slots(int64_t deg) {
     int64_t size = UTRI_HB;
     while (size < 3 * deg) size <<= 1;
     return size;
+}
+
+// A bucket takes 128 bytes of h_tab: its 8 keys, then their d values, then 32 bytes of
+// padding. The d of the first four slots, which hold the entries of all but crowded
+// buckets (slots fill in order), lie in the keys' 64-byte sector, so a hit reads no other
+// sector. Slot sl, counted like h_off, is slot sl % 8 of bucket sl / 8.
+constexpr int UTRI_HB_WORDS = 32;  // 32-bit words per bucket
+__host__ __device__ inline int64_t utri_hkey_index(int64_t sl) {
+    return (sl >> 3) * UTRI_HB_WORDS + (sl & 7);
+}
+__host__ __device__ inline int64_t utri_hd_index(int64_t sl) {  // in 8-byte words
+    return (sl >> 3) * (UTRI_HB_WORDS / 2) + 4 + (sl & 7);
 }
 
 // Home bucket of key in a table of 2^lgb buckets (lgb >= 0).

@@ -1316,7 +1316,7 @@ int utri_batch_launch(utri_graph* g, const WalkParams& wp_in, const int64_t* ite
     wp.qctr = (unsigned long long*)(const_cast<int64_t*>(n_items_dev) + 2);
     UTRI_TRY(utri_fill_u64(wp.qctr, 0, 2, s));
     SampleGraph G{g->m, g->e_lo, g->e_hi, g->e_d, g->inv, g->s_off, g->s_adj, g->s_d, g->h_off,
-                  g->h_key, g->h_d};
+                  g->h_tab};
     const int blocks = g->num_cu * blocks_per_cu(g, k_batch, TPB);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(TPB), 0, s, wp, g->o_off, g->o_adj, g->o_d,
                        len, (const uint2*)g->rinfo_cur, g->perm, items, n_items_dev, sp, G, slen);

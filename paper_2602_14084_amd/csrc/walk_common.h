@@ -162,8 +162,7 @@ struct SampleGraph {
     const int32_t* s_adj;
     const double* s_d;
     const int64_t* h_off;
-    const uint32_t* h_key;
-    const double* h_d;
+    const uint32_t* h_tab;
 };
 
 __device__ inline int log2_size(int64_t size) {
@@ -178,19 +177,24 @@ __device__ inline int hbuckets_lg(const SampleGraph& G, int32_t y) {
 }
 
 // Keys of bucket b (two 16-byte words) of the table at slot offset hoff.
-__device__ __forceinline__ const uint4* hbucket_ptr(const uint32_t* __restrict__ hkey, int64_t hoff,
+__device__ __forceinline__ const uint4* hbucket_ptr(const uint32_t* __restrict__ htab, int64_t hoff,
                                                     uint32_t b) {
-    return (const uint4*)(hkey + hoff + (int64_t)b * UTRI_HB);
+    return (const uint4*)(htab + ((hoff >> 3) + (int64_t)b) * UTRI_HB_WORDS);
+}
+
+// d of the edge to the neighbour in slot sl (a slot index from sym_lookup).
+__device__ __forceinline__ double sym_d(const uint32_t* __restrict__ htab, int64_t sl) {
+    return reinterpret_cast<const double*>(htab)[utri_hd_index(sl)];
 }
 
 // Slot of w in the symmetric row whose table (2^lgb buckets) starts at slot hoff, or -1.
 // A bucket whose last slot is empty ends the search (slots fill in order).
-__device__ inline int64_t sym_lookup(const uint32_t* __restrict__ hkey, int64_t hoff, int lgb,
+__device__ inline int64_t sym_lookup(const uint32_t* __restrict__ htab, int64_t hoff, int lgb,
                                      int32_t w) {
     const uint32_t mask = (1u << lgb) - 1u;
     uint32_t b = utri_hbucket(w, lgb);
     for (;;) {
-        const uint4* p = hbucket_ptr(hkey, hoff, b);
+        const uint4* p = hbucket_ptr(htab, hoff, b);
         const uint4 k0 = p[0], k1 = p[1];
         const int s = utri_hmatch(k0, k1, w);
         if (s >= 0) return hoff + (int64_t)b * UTRI_HB + s;
@@ -314,7 +318,7 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
                 k0[k] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
                 k1[k] = k0[k];
                 if (cand) {
-                    const uint4* p = hbucket_ptr(G.h_key, hoff, b[k]);
+                    const uint4* p = hbucket_ptr(G.h_tab, hoff, b[k]);
                     k0[k] = p[0];
                     k1[k] = p[1];
                 }
@@ -324,13 +328,13 @@ __device__ __forceinline__ void draw_row(const SampleParams& sp, const SampleGra
                 int s = utri_hmatch(k0[k], k1[k], w[k]);
                 while (s < 0 && k1[k].w != 0xFFFFFFFFu) {
                     b[k] = (b[k] + 1) & gm;
-                    const uint4* p = hbucket_ptr(G.h_key, hoff, b[k]);
+                    const uint4* p = hbucket_ptr(G.h_tab, hoff, b[k]);
                     k0[k] = p[0];
                     k1[k] = p[1];
                     s = utri_hmatch(k0[k], k1[k], w[k]);
                 }
                 hit[k] = s >= 0;
-                dy[k] = hit[k] ? G.h_d[hoff + (int64_t)b[k] * UTRI_HB + s] : 0.0;
+                dy[k] = hit[k] ? sym_d(G.h_tab, hoff + (int64_t)b[k] * UTRI_HB + s) : 0.0;
             }
         } else {
 #pragma unroll
