@@ -496,13 +496,13 @@ __device__ __forceinline__ void defer_drain(const WalkParams& wp, const double* 
     utri_wave_sync();
 }
 
-// The fill walk queues its hits per wave, in probe order, as (id of w, its class) or,
-// for a hit the codes leave undecided, (position of d_vw, class 3), and
-// writes them in batches: a wave waits for the permutation loads of its triangles' third
-// vertex (and the d loads of the undecided ones) once per batch instead of once per
-// strip. Written in queue order, the lists keep the order in which the strips were
-// probed. Queue words: vw = id of w or position of d_vw; ps = staged position | partner
-// slot << 15 | class << 21 (1 balanced, 2 unbalanced, 3 undecided).
+// The fill walk queues its hits per wave, in probe order, as (id of w, its class) or, for
+// a hit the codes leave undecided, (position of d_vw, class 3), and writes them in
+// batches: a wave waits for the permutation loads of its triangles' third vertex (and the
+// d loads of the undecided ones) once per batch instead of once per strip. Written in
+// queue order, the lists keep the order in which the strips were probed. Queue words:
+// vw = id of w or position of d_vw; ps = staged position | partner slot << 15 |
+// class << 21 (1 balanced, 2 unbalanced, 3 undecided).
 constexpr uint32_t FQ_BAL = 1u, FQ_UNBAL = 2u, FQ_UND = 3u;
 // A full queue is drained 64 entries at a time (the rest move to the front), so every
 // batch but an item's last fills the wave. 120 entries keep the fill walk's work-group
@@ -832,6 +832,83 @@ __device__ __forceinline__ void load_partners(const WalkParams& wp, const int32_
     }
 }
 
+// Counting walks: the partner rows of a batch that are at most one strip long are laid end
+// to end and probed 64 entries per strip, instead of one strip (and one round of per-row
+// broadcasts) each: at s23, t = 0.8, a third of the streamed rows are shorter than 64
+// entries. Lane l of packed strip k takes position P = 64 k + l of the concatenation; its
+// row is the partner r with the last start pre_r <= P (a binary search over the lanes'
+// exclusive prefix sums of the lengths), and the row's start and code thresholds come from
+// lane r. Undecided hits go to the deferred queue with r as their partner slot, like those
+// of whole strips. Rows this short are one strip long, so the Lemma-3 cut, which acts only
+// between batches of strips, never shortens them.
+template <int WOFF>
+__device__ __forceinline__ void walk_packed_rows(const WalkParams& wp, const double* __restrict__ o_d,
+                                                 const TabRef& R, int lv, int64_t ov, double duv,
+                                                 const CodeRow& cr, int nv, WalkLaneState& st) {
+    const int lane = utri_lane();
+    const int lvs = lv & 0xFFFF;
+    const int my_len = (lane < nv && lvs > 0 && lvs <= UTRI_WAVE) ? lvs : 0;
+    // inclusive prefix of the lengths over the lanes
+    int inc = my_len;
+#pragma unroll
+    for (int d = 1; d < UTRI_WAVE; d <<= 1) {
+        const int o = __shfl_up(inc, d, UTRI_WAVE);
+        if (lane >= d) inc += o;
+    }
+    const int pre = inc - my_len;  // exclusive
+    const int total = __shfl(inc, UTRI_WAVE - 1, UTRI_WAVE);
+    // (a lane with an empty row shares its start with the next lane, so the search below
+    // never ends on one: for P < total the last lane with pre_r <= P has P < pre_r + len_r)
+    for (int base = 0; base < total; base += UTRI_WAVE) {
+        const int P = base + lane;
+        const bool act = P < total;
+        // si: the last lane with pre_si <= P, whose row holds position P
+        int si = 0;
+#pragma unroll
+        for (int step = UTRI_WAVE / 2; step >= 1; step >>= 1) {
+            if (__shfl(pre, si + step, UTRI_WAVE) <= P) si += step;
+        }
+        const int64_t pos = __shfl(ov, si, UTRI_WAVE) + (P - __shfl(pre, si, UTRI_WAVE));
+        const uint32_t pw = act ? (uint32_t)wp.o_adj[pos] : 0u;
+        const uint32_t w = pw & wp.idmask;
+        const uint32_t r = tab_find<WOFF>(R.key, R.bmask, w);
+        const bool found = r != 0u;
+        const uint32_t khi = (uint32_t)__shfl((int)cr.khi, si, UTRI_WAVE);
+        const uint32_t klo = (uint32_t)__shfl((int)cr.klo, si, UTRI_WAVE);
+        const uint32_t rsign = (uint32_t)__shfl((int)cr.rsign, si, UTRI_WAVE);
+        const uint32_t qb = __builtin_amdgcn_ubfe(r, 16, QB);
+        const uint32_t qc = __builtin_amdgcn_ubfe(pw, wp.idbits, wp.mb);
+        const uint32_t p0 = __umul24(qb, qc);
+        const uint32_t t1 = p0 + qb + qc;  // (qb + 1)(qc + 1) - 1
+        // khi >= 1, so an absent w (r = 0, qb = 0) is never classified
+        const bool ccls = p0 >= khi;
+        const bool bal = ccls && (int32_t)(r ^ pw ^ rsign) < 0;
+        st.nb32 += bal ? 1u : 0u;
+        st.nu32 += ccls ? 1u : 0u;
+        const bool und = found && !ccls && t1 >= klo;
+        const uint64_t um = __builtin_amdgcn_ballot_w64(und);
+        if (um) {
+            const bool mine = (um >> lane) & 1ull;
+            const int nq = __popcll(um);
+            if (st.dn + nq <= DQ_CAP) {
+                if (mine) {
+                    DeferQueue& Q = defer_q[threadIdx.x / UTRI_WAVE];
+                    const int qs = st.dn + __popcll(um & __lanemask_lt());
+                    Q.vw[qs] = (uint32_t)pos;
+                    Q.ps[qs] = (r & W_POS) | ((uint32_t)si << 15);
+                }
+                st.dn += nq;
+            } else if (mine) {
+                const double s = utri_tri_s(__shfl(duv, si, UTRI_WAVE),
+                                            o_d[R.src_base + (r & W_POS)], o_d[pos]);
+                st.nb32 += (s <= -wp.c) ? 1u : 0u;
+                st.nu32 += (s <= -wp.c || s > wp.c) ? 1u : 0u;
+            }
+        }
+        if (st.dn > DQ_DRAIN) defer_drain(wp, o_d, R.src_base, duv, st);
+    }
+}
+
 #ifndef UTRI_WALK_MIN_WAVES
 #define UTRI_WALK_MIN_WAVES 8      // waves per SIMD the register allocation must allow
 #endif
@@ -859,12 +936,14 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
         const int nv = min(UTRI_WAVE, (np - i0 - part + nparts - 1) / nparts);
         // fill: the partners' original ids on their lanes (fill_drain reads them by slot)
         const int32_t pvl = (MODE == WALK_ENUM_FILL && lv != 0) ? perm[v] : 0;
+        constexpr bool kPack = MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT;
+        if (kPack) walk_packed_rows<WOFF>(wp, o_d, R, lv, ov, duv, cr, nv, st);
         // lane by lane (a loop over the set bits of a ballot made the sign-world walk slower
         // and the others no faster)
         for (int si = 0; si < nv; si++) {
             const int lvm = bcast_i32(lv, si);
             const int lvs = lvm & 0xFFFF;
-            if (lvs == 0) continue;
+            if (lvs == 0 || (kPack && lvs <= UTRI_WAVE)) continue;
             const int32_t pv = (MODE == WALK_ENUM_FILL) ? pvl
                                : (MODE == WALK_SIGN) ? bcast_i32(euv, si) : 0;
             const CodeRow crs{(uint32_t)bcast_i32((int)cr.khi, si),
