@@ -898,11 +898,15 @@ __device__ __forceinline__ void walk_packed_rows(const WalkParams& wp, const dou
                     Q.ps[qs] = (r & W_POS) | ((uint32_t)si << 15);
                 }
                 st.dn += nq;
-            } else if (mine) {
-                const double s = utri_tri_s(__shfl(duv, si, UTRI_WAVE),
-                                            o_d[R.src_base + (r & W_POS)], o_d[pos]);
-                st.nb32 += (s <= -wp.c) ? 1u : 0u;
-                st.nu32 += (s <= -wp.c || s > wp.c) ? 1u : 0u;
+            } else {
+                // every lane takes part in the shuffle (a lane shut off by a branch would
+                // hand its neighbours nothing); those with an undecided hit decide it now
+                const double duv_r = __shfl(duv, si, UTRI_WAVE);
+                if (mine) {
+                    const double s = utri_tri_s(duv_r, o_d[R.src_base + (r & W_POS)], o_d[pos]);
+                    st.nb32 += (s <= -wp.c) ? 1u : 0u;
+                    st.nu32 += (s <= -wp.c || s > wp.c) ? 1u : 0u;
+                }
             }
         }
         if (st.dn > DQ_DRAIN) defer_drain(wp, o_d, R.src_base, duv, st);
