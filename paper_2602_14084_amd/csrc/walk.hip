@@ -364,7 +364,8 @@ constexpr int SIGN_K = 16;   // bit planes of the sign-world counters (flush bef
 constexpr int SIGN_Q = 128;  // triangles queued per wave
 
 struct WalkLaneState {
-    uint32_t nb32 = 0, nu32 = 0;   // COUNT / ENUM_COUNT: balanced, classified (see item_counts)
+    uint64_t nb = 0, nu = 0;       // COUNT / ENUM_COUNT
+    uint32_t nb32 = 0, nu32 = 0;   // COUNT / ENUM_COUNT within one item: balanced, classified
     uint64_t tri = 0;              // EXPECTED / STATS
     uint64_t slo = 0;              // EXPECTED: sum of low 32 bits of each fixed-point term
     int64_t shi = 0;               // EXPECTED: sum of the terms shifted right by 32
@@ -966,31 +967,6 @@ __device__ __forceinline__ void walk_partners(const WalkParams& wp, const int32_
     }
 }
 
-// Add the wave's (balanced, classified) lane counters to the totals and clear them.
-__device__ __forceinline__ void count_flush(const WalkParams& wp, WalkLaneState& st) {
-    const uint64_t b = utri_wave_sum_u64(st.nb32), u = utri_wave_sum_u64(st.nu32 - st.nb32);
-    if (utri_lane() == 0) {
-        if (b) atomicAdd(&wp.acc[0], (unsigned long long)b);
-        if (u) atomicAdd(&wp.acc[1], (unsigned long long)u);
-    }
-    st.nb32 = st.nu32 = 0;
-}
-
-// Item end of the counting walks. An item adds at most its candidates to a lane's 32-bit
-// counters, far below 2^31: COUNT keeps them running across items and flushes the wave's
-// once any of them has passed 2^31, so none wraps (and at the end, walk_flush); ENUM_COUNT
-// writes the item's counts to its slot.
-template <int MODE>
-__device__ __forceinline__ void item_counts(const WalkParams& wp, int64_t slot, WalkLaneState& st) {
-    if (MODE == WALK_COUNT) {
-        if (__builtin_amdgcn_ballot_w64(st.nu32 >= 0x80000000u) != 0) count_flush(wp, st);
-    } else if (MODE == WALK_ENUM_COUNT) {
-        const uint64_t nb = utri_wave_sum_u64(st.nb32), nu = utri_wave_sum_u64(st.nu32 - st.nb32);
-        if (utri_lane() == 0) { wp.cnt_b[slot] = (int64_t)nb; wp.cnt_u[slot] = (int64_t)nu; }
-        st.nb32 = st.nu32 = 0;
-    }
-}
-
 // Wave item: vertex u with 2 <= len <= cap, N+(u) staged in the wave's own table, and
 // one range of its partners.
 template <int MODE, int PV, class G>
@@ -1021,7 +997,16 @@ __device__ void walk_item_wave(const WalkParams& wp, const int64_t* __restrict__
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[it]; run_u = wp.off_u[it]; }
     walk_partners<MODE, PV, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
                                        0, 1, H, st, run_b, run_u);
-    item_counts<MODE>(wp, it, st);
+    // an item counts at most its candidates per lane, far below 2^32; the counting walks
+    // keep (balanced, classified) per lane
+    st.nb += st.nb32;
+    st.nu += (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) ? st.nu32 - st.nb32 : st.nu32;
+    st.nb32 = st.nu32 = 0;
+    if (MODE == WALK_ENUM_COUNT) {
+        const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
+        if (lane == 0) { wp.cnt_b[it] = (int64_t)nb; wp.cnt_u[it] = (int64_t)nu; }
+        st.nb = st.nu = 0;
+    }
     utri_wave_sync();
 }
 
@@ -1035,6 +1020,7 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
                                 BlockTab<G>& B, HistLds* H, WalkLaneState& st) {
     constexpr bool shorter = (PV & 1) != 0;
     constexpr int WOFF = 4 << G::LGH;
+    const int lane = utri_lane();
     const int wib = threadIdx.x / UTRI_WAVE;
     const int u = item_vertex(item);
     const int chunk = item_chunk(item);
@@ -1061,14 +1047,27 @@ __device__ void walk_item_block(const WalkParams& wp, const int64_t* __restrict_
     if (MODE == WALK_ENUM_FILL) { run_b = wp.off_b[slot]; run_u = wp.off_u[slot]; }
     walk_partners<MODE, PV, WOFF>(wp, o_adj, o_d, rinfo, perm, R, u, Lu, sb, np, dmax_chunk,
                                        wib, G::NW, H, st, run_b, run_u);
-    item_counts<MODE>(wp, slot, st);
+    // an item counts at most its candidates per lane, far below 2^32; the counting walks
+    // keep (balanced, classified) per lane
+    st.nb += st.nb32;
+    st.nu += (MODE == WALK_COUNT || MODE == WALK_ENUM_COUNT) ? st.nu32 - st.nb32 : st.nu32;
+    st.nb32 = st.nu32 = 0;
+    if (MODE == WALK_ENUM_COUNT) {
+        const uint64_t nb = utri_wave_sum_u64(st.nb), nu = utri_wave_sum_u64(st.nu);
+        if (lane == 0) { wp.cnt_b[slot] = (int64_t)nb; wp.cnt_u[slot] = (int64_t)nu; }
+        st.nb = st.nu = 0;
+    }
 }
 
 template <int MODE>
 __device__ void walk_flush(const WalkParams& wp, HistLds* H, WalkLaneState& st) {
     const int lane = utri_lane();
     if (MODE == WALK_COUNT) {
-        count_flush(wp, st);
+        const uint64_t b = utri_wave_sum_u64(st.nb), u = utri_wave_sum_u64(st.nu);
+        if (lane == 0) {
+            if (b) atomicAdd(&wp.acc[0], (unsigned long long)b);
+            if (u) atomicAdd(&wp.acc[1], (unsigned long long)u);
+        }
     } else if (MODE == WALK_EXPECTED) {
         // lane value = shi * 2^32 + slo as a 128-bit two's complement number
         uint64_t lo = ((uint64_t)st.shi << 32);
