@@ -92,7 +92,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single "
+        print("bench.py measures one GPU only: the library runs the hot path on a single "
               "MI355X; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.only_main:
