@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_count_traffic.json")
+# the autotuner's choice for the benchmark graphs, written by utri_autotune on an MI355X
+TUNE_CACHE = os.path.join(ROOT, "profiles", "autotune_cache.jsonl")
 # the walk kernel and what fixes its inputs' layout (the row packing is done at ingest)
 WALK_SOURCES = ["paper_2602_14084_amd/csrc/walk.hip", "paper_2602_14084_amd/csrc/walk_common.h",
                 "paper_2602_14084_amd/csrc/utri_internal.h", "paper_2602_14084_amd/csrc/ingest.hip"]
@@ -82,6 +84,10 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="main count timing only")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="utri_autotune cache: a line for this graph shape is taken as it is, "
+                         "else the autotuner times its candidates and appends one")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-full", action="store_true",
@@ -125,6 +131,14 @@ def main():
     del src, dst, pp
     m_edges = g.m
     log(f"ingest {load_ms:.1f} ms, m={g.m}, max_deg={g.max_deg}")
+
+    # launch shape: the library's autotuner, for this graph at this threshold (set-up, not
+    # part of the timed region)
+    if not args.no_autotune:
+        t = time.perf_counter()
+        g.autotune(args.tau, args.tune_cache)
+        log(f"autotune {(time.perf_counter() - t) * 1e3:.0f} ms: {g.tuning()}")
+    tuning = g.tuning()
 
     method = utri.UTRI_PRUNED
     for _ in range(args.warmup):
@@ -233,7 +247,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "m": m_edges, "tau": args.tau, "method": "pruned",
                    "graph": f"R-MAT scale {args.scale}, edge factor 16, a=0.57 b=c=0.19, seed 1",
-                   "p_dist": "0.5*Beta(0.5,8)+0.5*Beta(8,0.5), seed 2"},
+                   "p_dist": "0.5*Beta(0.5,8)+0.5*Beta(8,0.5), seed 2", "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_walk<WALK_COUNT>", "kernel_ms": walk_ms,
